@@ -1,0 +1,217 @@
+"""Python access to the FP64 C oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg. The library and its Python binding never import
+this module. Nothing here shares code with the HIP path.
+
+Every wrapper takes numpy arrays, converts them to contiguous float64 / int32
+and returns freshly allocated numpy results.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (single-threaded, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "orc_validate": [C.c_int, i32, i64, P],
+            "orc_edges": [C.c_int, i32, i64, P, P, P, P, P],
+            "orc_csr": [i32, i64, P, P, P],
+            "orc_boundary": [C.c_int, i32, i64, P, P, P],
+            "orc_assemble": [C.c_int, i32, i64, P, P, P, P, f64, P, P],
+            "orc_edge_weights": [C.c_int, i32, i64, P, P, i64, P, P],
+            "orc_spmv": [i32, P, P, f64, P, f64, P, i32, P, P],
+            "orc_pcg": [i32, P, P, f64, P, f64, P, P, P, i32, P, P, f64, i32, P, P],
+            "orc_loss_grad_tri": [i32, i64, P, P, P, P, P],
+            "orc_loss_cstep_tri": [i32, i64, P, P, P, i32, i32, f64, P],
+            "orc_assemble_vjp_tri": [i32, i64, P, P, P, P, P, P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        names = {1: "INVALID_ARG", 2: "INDEX_RANGE", 3: "DEGENERATE", 4: "NOMEM"}
+        super().__init__(f"oracle {what}: {names.get(code, code)}")
+        self.code = code
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(code, what):
+    if code:
+        raise OracleError(code, what)
+
+
+def _dim(elem):
+    return 2 if elem.shape[1] == 3 else 3
+
+
+def validate(nV, elem):
+    elem = _i32(elem)
+    return lib().orc_validate(_dim(elem), nV, elem.shape[0], _p(elem))
+
+
+def edges(nV, elem):
+    """-> (EV (nE,2), elem_edge (n,nl), elem_sign (n,nl))"""
+    elem = _i32(elem)
+    dim = _dim(elem)
+    nl = 3 if dim == 2 else 6
+    cap = max(1, elem.shape[0] * nl)
+    EV = np.empty((cap, 2), np.int32)
+    ee = np.empty((elem.shape[0], nl), np.int32)
+    es = np.empty((elem.shape[0], nl), np.int8)
+    nE = C.c_int64(0)
+    _check(lib().orc_edges(dim, nV, elem.shape[0], _p(elem), _p(EV), C.byref(nE),
+                           _p(ee), _p(es)), "edges")
+    return EV[: nE.value].copy(), ee, es
+
+
+def csr(nV, EV):
+    EV = _i32(EV)
+    rowptr = np.empty(nV + 1, np.int32)
+    col = np.empty(nV + 2 * EV.shape[0], np.int32)
+    _check(lib().orc_csr(nV, EV.shape[0], _p(EV), _p(rowptr), _p(col)), "csr")
+    return rowptr, col
+
+
+def boundary(nV, elem):
+    elem = _i32(elem)
+    mask = np.empty(nV, np.uint8)
+    nb = C.c_int64(0)
+    _check(lib().orc_boundary(_dim(elem), nV, elem.shape[0], _p(elem), _p(mask),
+                              C.byref(nb)), "boundary")
+    return mask, nb.value
+
+
+def topology(nV, elem):
+    EV, ee, es = edges(nV, elem)
+    rowptr, col = csr(nV, EV)
+    return {"EV": EV, "elem_edge": ee, "elem_sign": es, "rowptr": rowptr, "col": col}
+
+
+def edge_weights(X, elem, EV=None, elem_edge=None):
+    X, elem = _f64(X), _i32(elem)
+    nV = X.shape[0]
+    if EV is None:
+        EV, elem_edge, _ = edges(nV, elem)
+    w = np.empty(EV.shape[0])
+    _check(lib().orc_edge_weights(_dim(elem), nV, elem.shape[0], _p(elem), _p(X),
+                                  EV.shape[0], _p(_i32(elem_edge)), _p(w)), "edge_weights")
+    return w
+
+
+def assemble(X, elem, rowptr=None, col=None, clamp_min=None):
+    """-> (Kvals (nnz,), Mdiag (nV,), rowptr, col)"""
+    X, elem = _f64(X), _i32(elem)
+    nV = X.shape[0]
+    if rowptr is None:
+        EV, _, _ = edges(nV, elem)
+        rowptr, col = csr(nV, EV)
+    rowptr, col = _i32(rowptr), _i32(col)
+    K = np.empty(int(rowptr[-1]))
+    M = np.empty(nV)
+    cm = -np.inf if clamp_min is None else float(clamp_min)
+    _check(lib().orc_assemble(_dim(elem), nV, elem.shape[0], _p(elem), _p(X), _p(rowptr),
+                              _p(col), cm, _p(K), _p(M)), "assemble")
+    return K, M, rowptr, col
+
+
+def spmv(rowptr, col, alpha, M, beta, K, x):
+    rowptr, col, M, K = _i32(rowptr), _i32(col), _f64(M), _f64(K)
+    x = _f64(x)
+    nV = rowptr.size - 1
+    k = 1 if x.ndim == 1 else x.shape[1]
+    y = np.empty_like(x)
+    _check(lib().orc_spmv(nV, _p(rowptr), _p(col), alpha, _p(M), beta, _p(K), k, _p(x),
+                          _p(y)), "spmv")
+    return y
+
+
+def pcg(rowptr, col, alpha, M, beta, K, b, u0=None, mask=None, g=None, rtol=1e-8,
+        max_iter=10000):
+    """-> (u, iters (k,), relres (k,))"""
+    rowptr, col, M, K = _i32(rowptr), _i32(col), _f64(M), _f64(K)
+    b = _f64(b)
+    nV = rowptr.size - 1
+    k = 1 if b.ndim == 1 else b.shape[1]
+    u = np.zeros_like(b) if u0 is None else _f64(u0).copy()
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        g = _f64(g).reshape(b.shape)
+    its = np.empty(k, np.int32)
+    rr = np.empty(k)
+    _check(lib().orc_pcg(nV, _p(rowptr), _p(col), alpha, _p(M), beta, _p(K), _p(mask),
+                         _p(g), k, _p(b), _p(u), rtol, max_iter, _p(its), _p(rr)), "pcg")
+    return u, its, rr
+
+
+def loss_grad_tri(X, F, u):
+    X, F, u = _f64(X), _i32(F), _f64(u)
+    g = np.empty_like(X)
+    L = C.c_double(0)
+    _check(lib().orc_loss_grad_tri(X.shape[0], F.shape[0], _p(F), _p(X), _p(u), C.byref(L),
+                                   _p(g)), "loss_grad_tri")
+    return L.value, g
+
+
+def loss_cstep_tri(X, F, u, v, c, h=1e-30):
+    X, F, u = _f64(X), _i32(F), _f64(u)
+    d = C.c_double(0)
+    _check(lib().orc_loss_cstep_tri(X.shape[0], F.shape[0], _p(F), _p(X), _p(u), v, c, h,
+                                    C.byref(d)), "loss_cstep_tri")
+    return d.value
+
+
+def assemble_vjp_tri(X, F, rowptr, col, gK=None, gM=None):
+    X, F = _f64(X), _i32(F)
+    gX = np.empty_like(X)
+    _check(lib().orc_assemble_vjp_tri(X.shape[0], F.shape[0], _p(F), _p(X), _p(_i32(rowptr)),
+                                      _p(_i32(col)), _p(None if gK is None else _f64(gK)),
+                                      _p(None if gM is None else _f64(gM)), _p(gX)),
+           "assemble_vjp_tri")
+    return gX

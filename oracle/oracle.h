@@ -1,0 +1,100 @@
+/*
+ * Oracle for the mesh-operator path: a plain, slow, single-threaded FP64 CPU
+ * implementation written from the paper's definitions.
+ *
+ * TEST INFRASTRUCTURE ONLY. It is called by the tests, by the smoke check and
+ * by the benchmark's CPU-baseline leg, never by the library itself. It shares
+ * no code, header, table or helper with the HIP library.
+ *
+ * Index arrays are int32, row-major: triangles (n_elem x 3), tetrahedra
+ * (n_elem x 4). Positions are double (nV x 3). Vectors with k right-hand sides
+ * are vertex-major (nV x k). All functions return 0 on success or one of the
+ * ORC_ERR_* codes; no function allocates memory it hands back.
+ */
+#ifndef DGO_ORACLE_H
+#define DGO_ORACLE_H
+#include <stdint.h>
+
+#define ORC_OK 0
+#define ORC_ERR_INVALID_ARG 1
+#define ORC_ERR_INDEX_RANGE 2
+#define ORC_ERR_DEGENERATE 3
+#define ORC_ERR_NOMEM 4
+
+/* Element indices in [0, nV) and pairwise distinct within each element. */
+int orc_validate(int dim, int32_t nV, int64_t n_elem, const int32_t *elem);
+
+/* Edges (Sec. 4.1 notation EV) and the element -> edge map (Sec. 6.1
+ * face-subface and subface-orientation tensors, d = 1 level).
+ *   EV        : out, capacity n_elem*nl*2, first 2*nE entries written, edges
+ *               as (min, max), sorted lexicographically; edge id = rank.
+ *   elem_edge : out, n_elem*nl. Triangles: slot j is the edge opposite local
+ *               vertex j, i.e. {v[j+1], v[j+2]} (indices mod 3).
+ *               Tetrahedra: slots are the local pairs 01,02,03,12,13,23.
+ *   elem_sign : out, n_elem*nl, +1 if the slot's local pair (first, second)
+ *               runs from the smaller to the larger vertex id, else -1.
+ *   nl = 3 (triangles) or 6 (tetrahedra). */
+int orc_edges(int dim, int32_t nV, int64_t n_elem, const int32_t *elem,
+              int32_t *EV, int64_t *nE, int32_t *elem_edge, int8_t *elem_sign);
+
+/* CSR pattern {(i,i)} U {(i,j),(j,i) : edge ij}, rows ascending, columns
+ * ascending within a row. rowptr: nV+1, col: nV + 2 nE. */
+int orc_csr(int32_t nV, int64_t nE, const int32_t *EV, int32_t *rowptr, int32_t *col);
+
+/* Boundary: triangle meshes mark the vertices of edges with one incident
+ * triangle; tetrahedral meshes mark the vertices of triangles that belong to
+ * one tetrahedron. mask: nV bytes (1 = boundary). n_bfaces: number of
+ * boundary edges (dim 2) or boundary triangles (dim 3). */
+int orc_boundary(int dim, int32_t nV, int64_t n_elem, const int32_t *elem,
+                 uint8_t *mask, int64_t *n_bfaces);
+
+/* Cotangent stiffness K (positive semidefinite, K_ij = -w_ij, K_ii = sum_j
+ * w_ij) in CSR order and the barycentric lumped mass M (diagonal).
+ * clamp_min: if > -inf, every per-edge weight w is replaced by max(w,
+ * clamp_min) before the diagonal is formed. Returns ORC_ERR_DEGENERATE if an
+ * element has zero measure (outputs are then unspecified). */
+int orc_assemble(int dim, int32_t nV, int64_t n_elem, const int32_t *elem,
+                 const double *X, const int32_t *rowptr, const int32_t *col,
+                 double clamp_min, double *Kvals, double *Mdiag);
+
+/* Per-edge weights w (indexed like EV) as the plain sum over elements. */
+int orc_edge_weights(int dim, int32_t nV, int64_t n_elem, const int32_t *elem,
+                     const double *X, int64_t nE, const int32_t *elem_edge,
+                     double *w);
+
+/* y = (alpha M + beta K) x for k columns (x, y: nV x k). */
+int orc_spmv(int32_t nV, const int32_t *rowptr, const int32_t *col,
+             double alpha, const double *Mdiag, double beta, const double *Kvals,
+             int32_t k, const double *x, double *y);
+
+/* Jacobi-preconditioned CG on (alpha M + beta K) u = b, per column, from the
+ * initial guess in u. With a Dirichlet mask (may be NULL) rows and columns
+ * of masked vertices are eliminated: b_I <- b_I - A_IB g_B, u_B = g_B.
+ * A column stops when ||r||_2 <= rtol ||b_eff||_2 (rtol <= 0: never) or
+ * after max_iter iterations. iters (k) and relres (k, recursive residual over
+ * ||b_eff||) are outputs and may be NULL. */
+int orc_pcg(int32_t nV, const int32_t *rowptr, const int32_t *col,
+            double alpha, const double *Mdiag, double beta, const double *Kvals,
+            const uint8_t *mask, const double *g, int32_t k, const double *b,
+            double *u, double rtol, int32_t max_iter, int32_t *iters,
+            double *relres);
+
+/* Triangle meshes: loss = u^T K(X) u + sum_T area_T and its gradient with
+ * respect to X (nV x 3), summed per element in ascending element order. */
+int orc_loss_grad_tri(int32_t nV, int64_t nF, const int32_t *F, const double *X,
+                      const double *u, double *loss, double *grad);
+
+/* Complex-step derivative of the same loss with respect to X[v, c]:
+ * Im(loss(X + i h e_vc)) / h. */
+int orc_loss_cstep_tri(int32_t nV, int64_t nF, const int32_t *F, const double *X,
+                       const double *u, int32_t v, int32_t c, double h,
+                       double *dloss);
+
+/* Vector-Jacobian product of triangle assembly:
+ * gX = (dKvals/dX)^T gK + (dMdiag/dX)^T gM; gK (CSR-aligned) or gM may be
+ * NULL (treated as zero). Unclamped weights. */
+int orc_assemble_vjp_tri(int32_t nV, int64_t nF, const int32_t *F, const double *X,
+                         const int32_t *rowptr, const int32_t *col,
+                         const double *gK, const double *gM, double *gX);
+
+#endif
