@@ -1,0 +1,254 @@
+/*
+ * dgo -- discrete geometry operators on simplicial meshes for MI355X (gfx950).
+ *
+ * C ABI of the library libdgo.so. It follows the statement of the problem in
+ * the paper "iskra: A System for Inverse Geometry Processing" (arXiv
+ * 2602.12105): a mesh is a set of simplices with unique indices and a
+ * canonical orientation (Sec. 4.1); its topology is the hierarchy of
+ * face-subface tensors (Sec. 6.1); per-element quantities are scattered down
+ * the hierarchy into vertex-indexed sparse operators (Sec. 5.1), the
+ * cotangent Laplacian and diagonal mass matrix of the MCF application
+ * (Sec. 7.1), which are then applied inside linear solves (Sec. 5.2) and
+ * differentiated with respect to the vertex positions (the df/dx term of the
+ * adjoint method, Sec. 3.1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named d_* are device pointers (HBM of the current HIP device);
+ *   h_* are host pointers. The caller owns every pointer it passes and keeps
+ *   it alive until the work enqueued on the stream has finished. The library
+ *   owns the storage inside dgo_mesh and dgo_server objects.
+ * - dgo_stream is a hipStream_t (NULL = the legacy default stream). Numeric
+ *   calls only enqueue work on that stream and return; they synchronise the
+ *   stream only when a host-side result pointer (h_*) is non-NULL or when
+ *   stated below.
+ * - Indices are int32; element arrays are row-major (n_elem x 3) for
+ *   triangles (dim = 2) and (n_elem x 4) for tetrahedra (dim = 3).
+ * - Vertex positions are (batch x nV x 3), row-major, in the call's dtype.
+ *   Vectors with k columns are vertex-major: (nV x k).
+ * - Operators use the CSR pattern of the mesh (dgo_mesh_csr): the stiffness
+ *   values Kvals are (batch x nnz) aligned with that pattern, the lumped mass
+ *   Mdiag is (batch x nV).
+ * - Sign convention: K is positive semidefinite, K_ij = -w_ij for an edge ij
+ *   and K_ii = sum_j w_ij, with w_ij = 1/2 (cot a_ij + cot b_ij) on triangle
+ *   meshes and the P1 stiffness on tetrahedra. The paper's Laplacian L of the
+ *   MCF equation (M - tau L) v' = M v is -K.
+ * - Every call returns a dgo_status. On failure nothing is enqueued, except
+ *   where noted, and dgo_last_error() returns a message for the calling
+ *   thread. No C++ exception crosses this boundary.
+ * - A mesh object may be used from one host thread at a time: the numeric
+ *   calls share a scratch workspace stored inside it.
+ */
+#ifndef DGO_H
+#define DGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *dgo_stream; /* hipStream_t */
+
+typedef enum {
+    DGO_OK = 0,
+    DGO_ERR_INVALID_ARG = 1,   /* bad pointer, size, dtype or option */
+    DGO_ERR_INDEX_RANGE = 2,   /* an element index outside [0, nV) */
+    DGO_ERR_DEGENERATE = 3,    /* an element of zero measure */
+    DGO_ERR_NOMEM = 4,         /* device allocation failed */
+    DGO_ERR_DEVICE = 5,        /* a HIP runtime error */
+    DGO_ERR_NOT_CONVERGED = 6, /* solver stopped early and strict was set */
+    DGO_ERR_BUDGET = 7,        /* request larger than the server's HBM budget */
+    DGO_ERR_UNSUPPORTED = 8,   /* valid input outside what this build handles */
+    DGO_ERR_TIMEOUT = 9,       /* a wait ran out of time */
+    DGO_ERR_SHUTDOWN = 10      /* server is shutting down */
+} dgo_status;
+
+typedef enum { DGO_F32 = 0, DGO_F64 = 1 } dgo_dtype;
+
+/* Optional device allocator; NULL means hipMallocAsync / hipFreeAsync on the
+ * stream given to the call that allocates. alloc returns NULL on failure. */
+typedef struct {
+    void *(*alloc)(size_t bytes, dgo_stream stream, void *ctx);
+    void (*free)(void *ptr, dgo_stream stream, void *ctx);
+    void *ctx;
+} dgo_allocator;
+
+typedef struct dgo_mesh dgo_mesh;
+
+typedef struct {
+    int32_t dim;        /* 2 triangles, 3 tetrahedra */
+    int32_t nV;         /* vertices */
+    int64_t n_elem;     /* triangles or tetrahedra */
+    int64_t nE;         /* edges */
+    int64_t nnz;        /* CSR entries = nV + 2 nE */
+    int64_t n_bfaces;   /* boundary edges (dim 2) or boundary triangles (dim 3) */
+    int64_t n_boundary; /* boundary vertices */
+    int32_t max_row;    /* longest CSR row (1 + vertex degree) */
+} dgo_sizes;
+
+/* ---------------------------------------------------------------- topology */
+
+/* Build the topology of a simplicial mesh (Sec. 4.1 simplex sets and EV, VV;
+ * Sec. 6.1 face-subface and subface-orientation tensors):
+ *   - edges EV as (min, max) vertex pairs sorted lexicographically, edge id =
+ *     rank (the canonical orientation is min -> max);
+ *   - the element -> edge map and its orientation signs;
+ *   - the CSR pattern {(i,i)} U VV with ascending columns per row;
+ *   - boundary vertices (edges of one triangle / triangles of one tetrahedron);
+ *   - the per-vertex incidence lists the assembly kernels read.
+ * d_elem: device, (n_elem x (dim+1)) int32, read during the call only (the
+ * library keeps its own copy). Every index must lie in [0, nV) and the
+ * vertices of an element must be distinct: otherwise DGO_ERR_INDEX_RANGE or
+ * DGO_ERR_INVALID_ARG. A vertex touched by no element is allowed (an isolated
+ * row holding only its diagonal). Rows longer than 255 entries (vertex degree
+ * above 254) return DGO_ERR_UNSUPPORTED.
+ * Synchronises the stream (sizes are needed on the host). On success *out is
+ * a new mesh owned by the caller, released with dgo_mesh_destroy. */
+dgo_status dgo_mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_t *d_elem,
+                           const dgo_allocator *alloc, dgo_stream stream, dgo_mesh **out);
+
+/* Release a mesh and its device storage (after synchronising its last
+ * stream). NULL is accepted. */
+void dgo_mesh_destroy(dgo_mesh *mesh);
+
+/* Host-side sizes; no device work. */
+dgo_status dgo_mesh_sizes(const dgo_mesh *mesh, dgo_sizes *out);
+
+/* Copy out the edge topology (any pointer may be NULL to skip it):
+ *   d_EV (nE x 2), d_elem_edge (n_elem x nl), d_elem_sign (n_elem x nl),
+ * nl = 3 for triangles (slot j = edge opposite local vertex j, the paper's
+ * rule that subface j is opposite vertex j) and 6 for tetrahedra (local pairs
+ * 01, 02, 03, 12, 13, 23). sign = +1 when the slot's local pair runs from the
+ * smaller to the larger vertex id. */
+dgo_status dgo_mesh_edges(const dgo_mesh *mesh, int32_t *d_EV, int32_t *d_elem_edge,
+                          int8_t *d_elem_sign, dgo_stream stream);
+
+/* Copy out the CSR pattern: d_rowptr (nV + 1), d_col (nnz). Either may be NULL. */
+dgo_status dgo_mesh_csr(const dgo_mesh *mesh, int32_t *d_rowptr, int32_t *d_col,
+                        dgo_stream stream);
+
+/* Copy out the boundary-vertex mask: d_mask (nV bytes, 1 = boundary). */
+dgo_status dgo_mesh_boundary(const dgo_mesh *mesh, uint8_t *d_mask, dgo_stream stream);
+
+/* ----------------------------------------------------------------- assembly */
+
+typedef struct {
+    /* Clamp of the per-edge weights (the clamp_min argument of the paper's
+     * cotan_weights, Sec. 4.2): when use_clamp != 0 every summed edge weight
+     * w is replaced by max(w, clamp_min) and the diagonal is formed from the
+     * clamped weights. */
+    int32_t use_clamp;
+    double clamp_min;
+} dgo_assemble_opts;
+
+/* Assemble the stiffness K and lumped mass M of `batch` meshes that share
+ * this topology (the cotangent Laplacian of the ARAP example, Sec. 4.2, and
+ * the Laplacian and diagonal mass matrix of the MCF application, Sec. 7.1):
+ *   triangles: w_ij = sum over triangles on edge ij of 1/2 cot(opposite angle),
+ *              M_ii = sum over incident triangles of area/3;
+ *   tetrahedra: w_ij = -sum over tets on edge ij of vol grad(phi_i).grad(phi_j),
+ *              M_ii = sum over incident tets of vol/4.
+ * d_X (batch x nV x 3), d_Kvals (batch x nnz), d_Mdiag (batch x nV) in dtype.
+ * opts may be NULL (no clamp). The result is bitwise deterministic and
+ * bitwise symmetric (K_ij == K_ji). If h_n_degenerate is non-NULL the call
+ * synchronises, stores the number of zero-measure elements (over the batch)
+ * and returns DGO_ERR_DEGENERATE when it is not zero; otherwise such elements
+ * silently produce non-finite values. */
+dgo_status dgo_assemble(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch, const void *d_X,
+                        const dgo_assemble_opts *opts, void *d_Kvals, void *d_Mdiag,
+                        int64_t *h_n_degenerate, dgo_stream stream);
+
+/* Vector-Jacobian product of dgo_assemble (unclamped) with respect to the
+ * vertex positions, for triangle meshes: the df/dx factor of the adjoint
+ * method (Sec. 3.1, Eq. implicit-full) for a relation whose matrices depend on
+ * the positions, as in the MCF application (Sec. 7.1):
+ *   d_gX = (dKvals/dX)^T gK + (dMdiag/dX)^T gM,
+ * d_gK (batch x nnz) and d_gM (batch x nV) may each be NULL (= zero);
+ * d_gX (batch x nV x 3) is overwritten. Deterministic. dim 3 meshes return
+ * DGO_ERR_UNSUPPORTED. */
+dgo_status dgo_assemble_vjp(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch,
+                            const void *d_X, const void *d_gK, const void *d_gM, void *d_gX,
+                            dgo_stream stream);
+
+/* --------------------------------------------------------- operator apply */
+
+/* y = (alpha M + beta K) x for `batch` operator instances and k columns:
+ * d_Mdiag (batch x nV), d_Kvals (batch x nnz), d_x and d_y (batch x nV x k),
+ * 1 <= k <= 64. d_y must not alias d_x. This is the operator application
+ * repeated inside the solves of Sec. 5.2. */
+dgo_status dgo_spmv(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch, double alpha,
+                    const void *d_Mdiag, double beta, const void *d_Kvals, int32_t k,
+                    const void *d_x, void *d_y, dgo_stream stream);
+
+typedef struct {
+    double rtol;          /* stop a column when ||r||_2 <= rtol ||b_eff||_2 */
+    int32_t max_iter;     /* iteration cap per column */
+    int32_t fixed_iters;  /* != 0: run exactly max_iter iterations, no test */
+    int32_t check_every;  /* host convergence poll period (iterations), >= 1 */
+    int32_t stall_iters;  /* > 0: also stop a column after this many
+                             iterations without a new smallest residual */
+    int32_t strict;       /* != 0: return DGO_ERR_NOT_CONVERGED if a column
+                             stops without meeting rtol (the paper's strict
+                             flag of its GMRES, Sec. 6.2) */
+} dgo_cg_opts;
+
+typedef struct {
+    int32_t k;
+    int32_t converged_all;  /* 1 if every column met rtol */
+    int32_t iters[64];      /* iterations per column */
+    double relres[64];      /* recursive residual / ||b_eff|| per column */
+    double true_relres[64]; /* ||b_eff - A u|| / ||b_eff|| evaluated in FP64 */
+} dgo_cg_report;
+
+/* Jacobi-preconditioned conjugate gradients (Saad, Alg. 9.1) on
+ * (alpha M + beta K) u = b for k independent columns (1 <= k <= 64), standing
+ * in for the linear solves of Sec. 5.2 and for the quadratic energy with
+ * fixed values of the ARAP step (Sec. 4.2). Columns stop independently and
+ * are frozen once stopped. d_Mdiag (nV), d_Kvals (nnz), d_b and d_u (nV x k);
+ * d_u holds the initial guess on entry and the solution on exit.
+ * Dirichlet data: when d_mask (nV bytes) is non-NULL, rows and columns of
+ * masked vertices are eliminated (b_I <- b_I - A_IB g_B) and u_B = g_B on
+ * exit, with d_g (nV x k). Vectors are in dtype; with F32 every dot product
+ * is accumulated in FP64. Reductions are in a fixed order: the result is
+ * bitwise deterministic. Polls the device every check_every iterations
+ * (synchronising the stream); h_rep (may be NULL) receives the report.
+ * Non-convergence returns DGO_OK unless opts->strict is set. */
+dgo_status dgo_pcg(const dgo_mesh *mesh, dgo_dtype dtype, double alpha, const void *d_Mdiag,
+                   double beta, const void *d_Kvals, const uint8_t *d_mask, const void *d_g,
+                   int32_t k, const void *d_b, void *d_u, const dgo_cg_opts *opts,
+                   dgo_cg_report *h_rep, dgo_stream stream);
+
+/* ----------------------------------------------------------------- tracing */
+
+/* Kernel timing for measurement (not part of the method). While enabled,
+ * every kernel the library launches whose name contains `filter` (NULL or ""
+ * = every kernel) is bracketed by a pair of hipEvents recorded on the stream
+ * it is launched on. dgo_trace_read synchronises those events and returns,
+ * per kernel name, the launch count and the summed and extreme durations.
+ * Process-wide and thread-safe. Disabling keeps the collected records. */
+typedef struct {
+    char name[48];
+    int64_t count;
+    double total_ms, min_ms, max_ms;
+} dgo_trace_entry;
+
+dgo_status dgo_trace_enable(int32_t on, const char *filter);
+/* Fill up to cap entries (sorted by total time, largest first); *n receives
+ * the number of distinct kernels seen. Pending records are consumed. */
+dgo_status dgo_trace_read(dgo_trace_entry *h_out, int32_t cap, int32_t *n);
+void dgo_trace_reset(void);
+
+/* ------------------------------------------------------------------ errors */
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char *dgo_last_error(void);
+
+/* Library version string. */
+const char *dgo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGO_H */

@@ -1,0 +1,246 @@
+"""dgo: discrete geometry operators on simplicial meshes for MI355X (gfx950).
+
+Thin Python binding over the C ABI of libdgo.so (include/dgo.h). It only
+marshals arguments: PyTorch supplies device memory and the current HIP stream,
+and every step of the computation runs in the library's HIP kernels.
+
+    mesh = Mesh(faces_cuda_int32, nV)            # topology on the device
+    K, M = assemble(mesh, X)                     # cotangent stiffness + mass
+    y = spmv(mesh, 1.0, M, 1e-3, K, x)           # (M + 1e-3 K) x
+    u, rep = pcg(mesh, 1.0, M, 1e-3, K, b)       # Jacobi PCG
+    K, M = AssembleFn.apply(X, mesh)             # differentiable in X
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from ._lib import (DGO_F32, DGO_F64, AssembleOpts, CgOpts, CgReport, DgoError, Sizes, check,
+                   lib)
+
+__all__ = ["Mesh", "assemble", "assemble_vjp", "spmv", "pcg", "AssembleFn", "DgoError",
+           "library_path", "build", "trace_enable", "trace_read", "trace_reset"]
+
+
+def build():
+    from .build import build as _b
+    return _b()
+
+
+def library_path():
+    from ._lib import LIB_PATH
+    return LIB_PATH
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(dt):
+    if dt == torch.float64:
+        return DGO_F64
+    if dt == torch.float32:
+        return DGO_F32
+    raise TypeError(f"dgo: unsupported dtype {dt} (float32 or float64)")
+
+
+def _need(t, name, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"dgo: {name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"dgo: {name} must be on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError(f"dgo: {name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"dgo: {name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"dgo: {name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Mesh:
+    """Topology of a triangle (elem: n x 3) or tetrahedral (n x 4) mesh."""
+
+    def __init__(self, elem: torch.Tensor, nV: int):
+        _need(elem, "elem", torch.int32)
+        if elem.dim() != 2 or elem.shape[1] not in (3, 4):
+            raise ValueError("dgo: elem must be (n, 3) or (n, 4)")
+        self.device = elem.device
+        h = C.c_void_p()
+        dim = 2 if elem.shape[1] == 3 else 3
+        check(lib().dgo_mesh_create(dim, int(nV), elem.shape[0], _ptr(elem), None, _stream(),
+                                    C.byref(h)), "dgo_mesh_create")
+        self._h = h
+        s = Sizes()
+        check(lib().dgo_mesh_sizes(h, C.byref(s)), "dgo_mesh_sizes")
+        self.dim, self.nV, self.n_elem = s.dim, s.nV, s.n_elem
+        self.nE, self.nnz, self.n_bfaces = s.nE, s.nnz, s.n_bfaces
+        self.n_boundary, self.max_row = s.n_boundary, s.max_row
+        self.nl = 3 if dim == 2 else 6
+
+    @property
+    def handle(self):
+        return self._h
+
+    def edges(self):
+        EV = torch.empty((self.nE, 2), dtype=torch.int32, device=self.device)
+        ee = torch.empty((self.n_elem, self.nl), dtype=torch.int32, device=self.device)
+        es = torch.empty((self.n_elem, self.nl), dtype=torch.int8, device=self.device)
+        check(lib().dgo_mesh_edges(self._h, _ptr(EV), _ptr(ee), _ptr(es), _stream()),
+              "dgo_mesh_edges")
+        return EV, ee, es
+
+    def csr(self):
+        rowptr = torch.empty(self.nV + 1, dtype=torch.int32, device=self.device)
+        col = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        check(lib().dgo_mesh_csr(self._h, _ptr(rowptr), _ptr(col), _stream()), "dgo_mesh_csr")
+        return rowptr, col
+
+    def boundary(self):
+        m = torch.empty(self.nV, dtype=torch.uint8, device=self.device)
+        check(lib().dgo_mesh_boundary(self._h, _ptr(m), _stream()), "dgo_mesh_boundary")
+        return m
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.current_stream(self.device).synchronize()
+            lib().dgo_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _batched(X, nV, name="X", last=3):
+    if X.dim() == 2:
+        return 1, False
+    if X.dim() == 3 and X.shape[1] == nV and X.shape[2] == last:
+        return X.shape[0], True
+    raise ValueError(f"dgo: {name} must be (nV, {last}) or (batch, nV, {last})")
+
+
+def assemble(mesh: Mesh, X: torch.Tensor, clamp_min=None, check_degenerate=False,
+             out=None):
+    """Cotangent stiffness K (CSR values, PSD) and lumped mass diag M."""
+    _need(X, "X")
+    b, batched = _batched(X, mesh.nV)
+    if not batched:
+        _need(X, "X", shape=(mesh.nV, 3))
+    dt = _dtype_code(X.dtype)
+    if out is None:
+        K = torch.empty((b, mesh.nnz) if batched else (mesh.nnz,), dtype=X.dtype, device=X.device)
+        M = torch.empty((b, mesh.nV) if batched else (mesh.nV,), dtype=X.dtype, device=X.device)
+    else:
+        K, M = out
+    opts = None
+    if clamp_min is not None:
+        opts = C.byref(AssembleOpts(1, float(clamp_min)))
+    nd = C.c_int64(0)
+    check(lib().dgo_assemble(mesh.handle, dt, b, _ptr(X), opts, _ptr(K), _ptr(M),
+                             C.byref(nd) if check_degenerate else None, _stream()), "dgo_assemble")
+    return K, M
+
+
+def assemble_vjp(mesh: Mesh, X, gK=None, gM=None):
+    _need(X, "X")
+    b, batched = _batched(X, mesh.nV)
+    dt = _dtype_code(X.dtype)
+    if gK is not None:
+        _need(gK, "gK", X.dtype)
+    if gM is not None:
+        _need(gM, "gM", X.dtype)
+    gX = torch.empty_like(X)
+    check(lib().dgo_assemble_vjp(mesh.handle, dt, b, _ptr(X), _ptr(gK), _ptr(gM), _ptr(gX),
+                                 _stream()), "dgo_assemble_vjp")
+    return gX
+
+
+def spmv(mesh: Mesh, alpha, M, beta, K, x, out=None):
+    """y = (alpha M + beta K) x; x is (nV,), (nV, k) or (batch, nV, k)."""
+    _need(M, "M")
+    _need(K, "K", M.dtype)
+    _need(x, "x", M.dtype)
+    if x.dim() == 1:
+        b, k = 1, 1
+    elif x.dim() == 2:
+        b, k = 1, x.shape[1]
+    else:
+        b, k = x.shape[0], x.shape[2]
+    y = torch.empty_like(x) if out is None else out
+    check(lib().dgo_spmv(mesh.handle, _dtype_code(M.dtype), b, float(alpha), _ptr(M), float(beta),
+                         _ptr(K), k, _ptr(x), _ptr(y), _stream()), "dgo_spmv")
+    return y
+
+
+def pcg(mesh: Mesh, alpha, M, beta, K, b, u0=None, mask=None, g=None, rtol=1e-8,
+        max_iter=1000, fixed_iters=False, check_every=8, stall_iters=0, strict=False):
+    """Jacobi PCG on (alpha M + beta K) u = b; returns (u, report dict)."""
+    _need(M, "M")
+    _need(K, "K", M.dtype)
+    _need(b, "b", M.dtype)
+    k = 1 if b.dim() == 1 else b.shape[1]
+    u = torch.zeros_like(b) if u0 is None else u0.clone()
+    if mask is not None:
+        _need(mask, "mask", torch.uint8)
+        _need(g, "g", M.dtype, b.shape)
+    opts = CgOpts(float(rtol), int(max_iter), int(bool(fixed_iters)), int(check_every),
+                  int(stall_iters), int(bool(strict)))
+    rep = CgReport()
+    check(lib().dgo_pcg(mesh.handle, _dtype_code(M.dtype), float(alpha), _ptr(M), float(beta),
+                        _ptr(K), _ptr(mask), _ptr(g), k, _ptr(b), _ptr(u), C.byref(opts),
+                        C.byref(rep), _stream()), "dgo_pcg")
+    report = {"converged_all": bool(rep.converged_all), "iters": list(rep.iters[:k]),
+              "relres": list(rep.relres[:k]), "true_relres": list(rep.true_relres[:k])}
+    return u, report
+
+
+class AssembleFn(torch.autograd.Function):
+    """(K, M) = assemble(mesh, X) with a hand-written adjoint in X (triangles)."""
+
+    @staticmethod
+    def forward(ctx, X, mesh):
+        K, M = assemble(mesh, X.detach().contiguous())
+        ctx.mesh = mesh
+        ctx.save_for_backward(X)
+        return K, M
+
+    @staticmethod
+    def backward(ctx, gK, gM):
+        (X,) = ctx.saved_tensors
+        gK = None if gK is None else gK.contiguous()
+        gM = None if gM is None else gM.contiguous()
+        gX = assemble_vjp(ctx.mesh, X.detach().contiguous(), gK, gM)
+        return gX, None
+
+
+def trace_enable(on=True, name_filter=None):
+    """Bracket the library's kernel launches with hipEvents (measurement aid)."""
+    f = None if name_filter is None else name_filter.encode()
+    check(lib().dgo_trace_enable(int(bool(on)), f), "dgo_trace_enable")
+
+
+def trace_read():
+    """-> {kernel name: {count, total_ms, min_ms, max_ms, avg_ms}} (consumes pending records)."""
+    from ._lib import TraceEntry
+    cap = 64
+    arr = (TraceEntry * cap)()
+    n = C.c_int32(0)
+    check(lib().dgo_trace_read(arr, cap, C.byref(n)), "dgo_trace_read")
+    out = {}
+    for i in range(min(cap, n.value)):
+        e = arr[i]
+        out[e.name.decode()] = {"count": e.count, "total_ms": e.total_ms, "min_ms": e.min_ms,
+                                "max_ms": e.max_ms, "avg_ms": e.total_ms / max(1, e.count)}
+    return out
+
+
+def trace_reset():
+    lib().dgo_trace_reset()

@@ -1,0 +1,126 @@
+"""ctypes declarations of the C ABI in include/dgo.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgo.so")
+
+P = C.c_void_p
+i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+
+STATUS = {
+    0: "OK", 1: "INVALID_ARG", 2: "INDEX_RANGE", 3: "DEGENERATE", 4: "NOMEM", 5: "DEVICE",
+    6: "NOT_CONVERGED", 7: "BUDGET", 8: "UNSUPPORTED", 9: "TIMEOUT", 10: "SHUTDOWN",
+}
+DGO_F32, DGO_F64 = 0, 1
+
+
+class DgoError(RuntimeError):
+    def __init__(self, code: int, fn: str, msg: str):
+        super().__init__(f"{fn}: DGO_ERR_{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Sizes(C.Structure):
+    _fields_ = [("dim", i32), ("nV", i32), ("n_elem", i64), ("nE", i64), ("nnz", i64),
+                ("n_bfaces", i64), ("n_boundary", i64), ("max_row", i32)]
+
+
+class AssembleOpts(C.Structure):
+    _fields_ = [("use_clamp", i32), ("clamp_min", f64)]
+
+
+class CgOpts(C.Structure):
+    _fields_ = [("rtol", f64), ("max_iter", i32), ("fixed_iters", i32), ("check_every", i32),
+                ("stall_iters", i32), ("strict", i32)]
+
+
+class CgReport(C.Structure):
+    _fields_ = [("k", i32), ("converged_all", i32), ("iters", i32 * 64), ("relres", f64 * 64),
+                ("true_relres", f64 * 64)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("dtype", i32), ("max_slots", i32), ("hbm_budget_bytes", i64),
+                ("cg_iters", i32), ("cg_chunk", i32), ("alpha", f64), ("beta", f64),
+                ("max_batch_rows", i64), ("batched", i32), ("pad", i32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("dim", i32), ("nV", i32), ("n_elem", i64), ("k", i32), ("pad", i32),
+                ("h_elem", P), ("h_X", P), ("h_b", P), ("h_u", P), ("user", C.c_uint64)]
+
+
+class ReqStats(C.Structure):
+    _fields_ = [("status", i32), ("slot", i32), ("t_submit", f64), ("t_admit", f64),
+                ("t_start", f64), ("t_done", f64), ("iters", i32), ("pad", i32),
+                ("footprint", i64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", i64), ("admitted", i64), ("completed", i64), ("rejected", i64),
+                ("failed", i64), ("queue_depth", i64), ("active", i64), ("hbm_in_use", i64),
+                ("hbm_peak", i64), ("ticks", i64), ("batched_launches", i64), ("busy_s", f64)]
+
+
+class TraceEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("count", i64), ("total_ms", f64), ("min_ms", f64),
+                ("max_ms", f64)]
+
+
+SIGNATURES = {
+    "dgo_mesh_create": (C.c_int, [i32, i32, i64, P, P, P, C.POINTER(P)]),
+    "dgo_mesh_destroy": (None, [P]),
+    "dgo_mesh_sizes": (C.c_int, [P, C.POINTER(Sizes)]),
+    "dgo_mesh_edges": (C.c_int, [P, P, P, P, P]),
+    "dgo_mesh_csr": (C.c_int, [P, P, P, P]),
+    "dgo_mesh_boundary": (C.c_int, [P, P, P]),
+    "dgo_assemble": (C.c_int, [P, C.c_int, i32, P, C.POINTER(AssembleOpts), P, P,
+                               C.POINTER(i64), P]),
+    "dgo_assemble_vjp": (C.c_int, [P, C.c_int, i32, P, P, P, P, P]),
+    "dgo_spmv": (C.c_int, [P, C.c_int, i32, f64, P, f64, P, i32, P, P, P]),
+    "dgo_pcg": (C.c_int, [P, C.c_int, f64, P, f64, P, P, P, i32, P, P, C.POINTER(CgOpts),
+                          C.POINTER(CgReport), P]),
+    "dgo_trace_enable": (C.c_int, [i32, C.c_char_p]),
+    "dgo_trace_read": (C.c_int, [C.POINTER(TraceEntry), i32, C.POINTER(i32)]),
+    "dgo_trace_reset": (None, []),
+    "dgo_last_error": (C.c_char_p, []),
+    "dgo_version": (C.c_char_p, []),
+}
+
+SERVER_SIGNATURES = {
+    "dgo_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(P)]),
+    "dgo_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+    "dgo_server_wait": (C.c_int, [P, C.c_uint64, f64, C.POINTER(ReqStats)]),
+    "dgo_server_stats": (C.c_int, [P, C.POINTER(ServerStats)]),
+    "dgo_server_destroy": (None, [P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libdgo.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2602_12105_amd.build` "
+                "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in {**SIGNATURES, **SERVER_SIGNATURES}.items():
+            fn = getattr(L, name, None)
+            if fn is None:
+                continue
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int, fn: str):
+    if code != 0:
+        raise DgoError(code, fn, (lib().dgo_last_error() or b"").decode())

@@ -1,0 +1,141 @@
+// Internal declarations of libdgo (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/dgo.h"
+
+namespace dgo {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string &msg);
+void clear_error();
+
+// A failed HIP call becomes DGO_ERR_DEVICE (or NOMEM) with the message kept.
+dgo_status hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define DGO_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess) return ::dgo::hip_fail(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define DGO_TRY(call)                          \
+    do {                                       \
+        dgo_status s_ = (call);                \
+        if (s_ != DGO_OK) return s_;           \
+    } while (0)
+
+inline dgo_status fail(dgo_status s, const std::string &msg) {
+    set_error(msg);
+    return s;
+}
+
+// --------------------------------------------------------------- tracing
+
+// Brackets one kernel launch with hipEvents when tracing is on and the name
+// matches the filter (see dgo_trace_enable).
+struct TraceScope {
+    const char *name;
+    hipStream_t stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    TraceScope(const char *n, hipStream_t s);
+    ~TraceScope();
+};
+
+#define DGO_LAUNCH(name, stream, ...)               \
+    do {                                            \
+        ::dgo::TraceScope trace_scope_(name, stream); \
+        __VA_ARGS__;                                \
+    } while (0)
+
+// ------------------------------------------------------------ allocation
+
+struct Alloc {
+    dgo_allocator user{};
+    bool has_user = false;
+    void *get(size_t bytes, hipStream_t s) const;
+    void put(void *p, hipStream_t s) const;
+};
+
+// --------------------------------------------------------------- mesh
+
+// Rows per workgroup of the row-centric kernels and the LDS they need are
+// fixed at mesh creation from the longest block of rows.
+struct dgo_mesh_impl;
+
+}  // namespace dgo
+
+struct dgo_mesh {
+    int32_t dim = 0;       // 2 or 3
+    int32_t nv_elem = 0;   // 3 or 4 vertices per element
+    int32_t nl = 0;        // 3 or 6 edges per element
+    int32_t nV = 0;
+    int64_t n_elem = 0;
+    int64_t nE = 0;
+    int64_t nnz = 0;
+    int64_t n_inc = 0;     // vertex-element incidences = n_elem * nv_elem
+    int64_t n_bfaces = 0;
+    int64_t n_boundary = 0;
+    int32_t max_row = 0;
+    int device = 0;
+    dgo::Alloc alloc;
+    hipStream_t home = nullptr;  // stream of creation (used for frees)
+
+    // device topology
+    int32_t *elem = nullptr;       // n_elem x nv_elem
+    int32_t *EV = nullptr;         // nE x 2
+    int32_t *elem_edge = nullptr;  // n_elem x nl
+    int8_t *elem_sign = nullptr;   // n_elem x nl
+    int32_t *rowptr = nullptr;     // nV + 1
+    int32_t *col = nullptr;        // nnz
+    int32_t *diag = nullptr;       // nV, CSR slot of (i, i)
+    int32_t *vtptr = nullptr;      // nV + 1, incidence offsets
+    uint32_t *inc = nullptr;       // n_inc packed incidence records
+    uint8_t *bmask = nullptr;      // nV boundary mask
+
+    // row blocks for the row-centric kernels
+    int32_t rpb = 0;            // rows per workgroup
+    int32_t nblocks = 0;        // ceil(nV / rpb)
+    int32_t max_block_nnz = 0;  // largest CSR span of one block of rows
+
+    // scratch workspace reused by numeric calls (grows on demand)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+namespace dgo {
+
+// Grow the mesh workspace to at least `bytes`; contents are not preserved.
+dgo_status mesh_workspace(dgo_mesh *m, size_t bytes, hipStream_t s, void **out);
+
+// Exclusive prefix sum of n int32 values into out[0..n]; out[n] = total.
+// `tmp` must hold scan_tmp_elems(n) int32. in and out may alias.
+size_t scan_tmp_elems(int64_t n);
+dgo_status exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp,
+                          hipStream_t s);
+
+inline unsigned grid_for(int64_t n, int threads) {
+    int64_t g = (n + threads - 1) / threads;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Map a workgroup id to a logical tile so that each of the 8 XCDs (which get
+// workgroups round-robin) works on one contiguous range of tiles: neighbouring
+// tiles then share an L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nb) {
+    constexpr uint32_t NX = 8;
+    uint32_t per = nb / NX, rem = nb % NX;
+    uint32_t x = bid % NX, q = bid / NX;
+    // XCD x receives tiles [start_x, start_x + count_x)
+    uint32_t start = x * per + (x < rem ? x : rem);
+    uint32_t count = per + (x < rem ? 1u : 0u);
+    return q < count ? start + q : bid;  // bid >= NX*per + rem cannot happen
+}
+
+}  // namespace dgo

@@ -1,0 +1,62 @@
+"""Shared helpers of the tests: the row-scaled comparison metrics and mesh
+recipes. No arithmetic of the method lives here."""
+import numpy as np
+
+import meshgen
+
+RTOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def rows_of(rowptr):
+    rowptr = np.asarray(rowptr)
+    return np.repeat(np.arange(rowptr.size - 1), np.diff(rowptr))
+
+
+def assert_csr_close(got, ref, rowptr, rtol, what="K"):
+    """|got - ref| <= rtol * max_j |ref_ij| over the row (row-scaled)."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    rowptr = np.asarray(rowptr)
+    srow = np.maximum.reduceat(np.abs(ref), rowptr[:-1])
+    lim = rtol * srow[rows_of(rowptr)]
+    err = np.abs(got - ref)
+    bad = np.nonzero(~(err <= lim))[0]
+    assert bad.size == 0, (f"{what}: {bad.size} entries off; worst at {bad[:5]}: "
+                           f"got {got[bad[:5]]} ref {ref[bad[:5]]} lim {lim[bad[:5]]}")
+
+
+def assert_vec_close(got, ref, rtol, scale=None, what="v"):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    s = np.abs(ref) if scale is None else scale
+    err = np.abs(got - ref)
+    bad = np.nonzero(~(err <= rtol * s))[0] if np.ndim(s) else np.nonzero(~(err <= rtol * s))
+    assert np.size(bad) == 0, f"{what}: max err {err.max()} vs scale {np.max(s)}"
+
+
+def spmv_scale(rowptr, col, alpha, M, beta, K, x):
+    """sum_j |A_ij| |x_j| per row and column, the SpMV error scale."""
+    rowptr, col = np.asarray(rowptr), np.asarray(col)
+    rows = rows_of(rowptr)
+    a = np.abs(beta * K) + np.where(col == rows, np.abs(alpha * M[rows]), 0.0)
+    x = np.abs(x.reshape(rowptr.size - 1, -1))
+    out = np.zeros_like(x)
+    np.add.at(out, rows, a[:, None] * x[col])
+    return out
+
+
+MESHES = {
+    "tri1": lambda: (np.array([[0.0, 0, 0], [1, 0, 0], [0.2, 0.9, 0]]), np.array([[0, 1, 2]], np.int32)),
+    "tet1": lambda: (np.array([[0.0, 0, 0], [1, 0, 0], [0.1, 1, 0], [0.2, 0.3, 1]]),
+                     np.array([[0, 1, 2, 3]], np.int32)),
+    "disjoint": lambda: (np.random.default_rng(0).normal(size=(7, 3)),
+                         np.array([[0, 1, 2], [5, 4, 3]], np.int32)),
+    "fan": lambda: (np.random.default_rng(1).normal(size=(9, 3)),
+                    np.array([[0, i, i + 1] for i in range(1, 8)], np.int32)),
+    "grid64": lambda: meshgen.grid2d(64, 0.2, 0),
+    "grid7": lambda: meshgen.grid2d(7, 0.2, 1),
+    "ico3": lambda: meshgen.icosphere(3, 1e-3, 0),
+    "ico5": lambda: meshgen.icosphere(5, 1e-2, 0),
+    "ico7": lambda: meshgen.icosphere(7, 1e-3, 0),
+    "cube3": lambda: meshgen.cube_tets(3, 0.15, 0),
+    "cube9": lambda: meshgen.cube_tets(9, 0.15, 0),
+    "cube64": lambda: meshgen.cube_tets(64, 0.15, 0),
+}

@@ -1,0 +1,297 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Integers (edges, element->edge map, signs, CSR, boundary) must match bit for
+bit. Floats use the row-scaled metric: |got - ref| <= rtol * max_j |ref_ij|
+over the row, rtol = 1e-12 (FP64) or 1e-5 (FP32); in FP32 the oracle runs in
+FP64 on the same FP32-rounded positions.
+"""
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+from helpers import MESHES, RTOL, assert_csr_close, spmv_scale
+
+pytestmark = pytest.mark.gpu
+
+dgo = pytest.importorskip("paper_2602_12105_amd")
+DEV = "cuda:0"
+
+
+def _mesh(name):
+    X, E = MESHES[name]()
+    E_d = torch.from_numpy(E).to(DEV)
+    return X, E, dgo.Mesh(E_d, X.shape[0])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    import paper_2602_12105_amd._lib as L
+    L.lib()  # the native library must load; there is no fallback
+    yield
+
+
+@pytest.mark.parametrize("name", ["tri1", "tet1", "disjoint", "fan", "grid7", "grid64", "ico3",
+                                  "ico7", "cube3", "cube9", "cube64"])
+def test_topology_bit_exact(name):
+    print(f"[topology] {name}", flush=True)
+    X, E, m = _mesh(name)
+    nV = X.shape[0]
+    EV, ee, es = oracle.edges(nV, E)
+    rp, col = oracle.csr(nV, EV)
+    mask, nb = oracle.boundary(nV, E)
+    gEV, gee, ges = [t.cpu().numpy() for t in m.edges()]
+    grp, gcol = [t.cpu().numpy() for t in m.csr()]
+    assert m.nE == EV.shape[0] and m.nnz == col.size and m.n_bfaces == nb
+    np.testing.assert_array_equal(gEV, EV)
+    np.testing.assert_array_equal(gee, ee)
+    np.testing.assert_array_equal(ges, es)
+    np.testing.assert_array_equal(grp, rp)
+    np.testing.assert_array_equal(gcol, col)
+    np.testing.assert_array_equal(m.boundary().cpu().numpy(), mask)
+    assert m.n_boundary == int(mask.sum())
+
+
+def test_mesh_errors():
+    F = torch.tensor([[0, 1, 2], [2, 1, 7]], dtype=torch.int32, device=DEV)
+    with pytest.raises(dgo.DgoError) as e:
+        dgo.Mesh(F, 5)
+    assert e.value.status == "INDEX_RANGE"
+    F = torch.tensor([[0, 1, 1]], dtype=torch.int32, device=DEV)
+    with pytest.raises(dgo.DgoError) as e:
+        dgo.Mesh(F, 5)
+    assert e.value.status == "INVALID_ARG"
+    # degree above 254 is reported as unsupported
+    n = 300
+    F = torch.tensor([[0, i, i + 1] for i in range(1, n)], dtype=torch.int32, device=DEV)
+    with pytest.raises(dgo.DgoError) as e:
+        dgo.Mesh(F, n + 1)
+    assert e.value.status == "UNSUPPORTED"
+
+
+def _assemble_check(name, dtype, batch=1, clamp=None):
+    X, E, m = _mesh(name)
+    nV = X.shape[0]
+    Xs = [X]
+    for b in range(1, batch):
+        Xs.append(X * (1.0 + 0.01 * meshgen.normal(500 + b, nV))[:, None])
+    Xb = np.stack(Xs)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    Xd = torch.from_numpy(Xb).to(DEV, td)
+    Xref = Xd.double().cpu().numpy()  # FP32-rounded positions for the FP32 case
+    K, M = dgo.assemble(m, Xd, clamp_min=clamp, check_degenerate=True)
+    K = K.double().cpu().numpy()
+    M = M.double().cpu().numpy()
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    for b in range(batch):
+        Ko, Mo, rpo, colo = oracle.assemble(Xref[b], E, rp, col, clamp_min=clamp)
+        assert_csr_close(K[b], Ko, rp, RTOL[dtype], f"K[{b}]")
+        np.testing.assert_allclose(M[b], Mo, rtol=RTOL[dtype], atol=0)
+        # bitwise symmetry: K_ij == K_ji
+        rows = np.repeat(np.arange(nV), np.diff(rp))
+        key = {(int(i), int(j)): v for i, j, v in zip(rows[:5000], col[:5000], K[b][:5000])}
+        for (i, j), v in key.items():
+            if (j, i) in key:
+                assert v == key[(j, i)]
+    return m, Xd, K
+
+
+@pytest.mark.parametrize("name", ["tri1", "tet1", "disjoint", "fan", "grid7", "grid64", "ico3",
+                                  "ico7", "cube3", "cube9", "cube64"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_assemble_parity(name, dtype):
+    print(f"[assemble] {name} {dtype}", flush=True)
+    _assemble_check(name, dtype)
+
+
+@pytest.mark.parametrize("name", ["ico5", "cube9"])
+def test_assemble_batch_and_clamp(name):
+    print(f"[assemble-batch] {name}", flush=True)
+    _assemble_check(name, "f64", batch=3)
+    _assemble_check(name, "f64", batch=2, clamp=0.05 if name == "ico5" else 0.001)
+
+
+def test_assemble_symmetry_full_and_determinism():
+    X, E, m = _mesh("ico7")
+    Xd = torch.from_numpy(X).to(DEV)
+    K1, M1 = dgo.assemble(m, Xd)
+    K2, M2 = dgo.assemble(m, Xd)
+    assert torch.equal(K1, K2) and torch.equal(M1, M2)
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    K = K1.cpu().numpy()
+    rows = np.repeat(np.arange(X.shape[0]), np.diff(rp))
+    # mirror slot of (i, j) by searching row j
+    order = np.lexsort((rows, col))  # sorted by (col, row) -> transposed order
+    np.testing.assert_array_equal(K[order], K)
+
+
+def test_degenerate_reported():
+    X = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0, 1, 0]], float)
+    F = torch.tensor([[0, 1, 2], [0, 1, 3]], dtype=torch.int32, device=DEV)
+    m = dgo.Mesh(F, 4)
+    with pytest.raises(dgo.DgoError) as e:
+        dgo.assemble(m, torch.from_numpy(X).to(DEV), check_degenerate=True)
+    assert e.value.status == "DEGENERATE"
+
+
+@pytest.mark.parametrize("name", ["grid64", "ico5", "cube9"])
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 16])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmv_parity(name, k, dtype):
+    print(f"[spmv] {name} k={k} {dtype}", flush=True)
+    X, E, m = _mesh(name)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    K, M = dgo.assemble(m, torch.from_numpy(X).to(DEV, td))
+    x = (meshgen.uniform(1, X.shape[0] * k).reshape(-1, k) * 2 - 1)
+    xd = torch.from_numpy(x).to(DEV, td)
+    y = dgo.spmv(m, 0.7, M, 1.3, K, xd).double().cpu().numpy()
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    Kh, Mh, xh = K.double().cpu().numpy(), M.double().cpu().numpy(), xd.double().cpu().numpy()
+    yo = oracle.spmv(rp, col, 0.7, Mh, 1.3, Kh, xh).reshape(y.shape)
+    sc = spmv_scale(rp, col, 0.7, Mh, 1.3, Kh, xh).reshape(y.shape)
+    assert np.all(np.abs(y - yo) <= RTOL[dtype] * sc)
+
+
+def test_spmv_batch():
+    X, E, m = _mesh("ico3")
+    Xb = torch.from_numpy(np.stack([X, 1.1 * X])).to(DEV)
+    K, M = dgo.assemble(m, Xb)
+    x = torch.from_numpy(meshgen.normal(3, 2 * X.shape[0] * 4).reshape(2, -1, 4)).to(DEV)
+    y = dgo.spmv(m, 1.0, M, 1e-3, K, x)
+    for b in range(2):
+        yb = dgo.spmv(m, 1.0, M[b].contiguous(), 1e-3, K[b].contiguous(), x[b].contiguous())
+        assert torch.equal(yb, y[b])
+
+
+def _cfg2_system(level, k, dtype, seed=1):
+    X, F = meshgen.icosphere(level, 1e-3, 0)
+    m = dgo.Mesh(torch.from_numpy(F).to(DEV), X.shape[0])
+    td = torch.float64 if dtype == "f64" else torch.float32
+    K, M = dgo.assemble(m, torch.from_numpy(X).to(DEV, td))
+    f = torch.from_numpy(meshgen.normal(seed, X.shape[0] * k).reshape(-1, k)).to(DEV, td)
+    b = (M[:, None] * f).contiguous()
+    return m, K, M, b
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pcg_fixed_iterations_match_oracle(dtype):
+    """The same iteration count on both sides: iterates agree element by element."""
+    print(f"[pcg-fixed] {dtype}", flush=True)
+    m, K, M, b = _cfg2_system(5, 8, dtype)
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=30, fixed_iters=True)
+    assert rep["iters"] == [30] * 8
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    uo, its, rr = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3,
+                             K.double().cpu().numpy(), b.double().cpu().numpy(), rtol=0.0,
+                             max_iter=30)
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
+    assert err <= tol, err
+
+
+def test_pcg_converges_cfg2_f64():
+    print("[pcg] icosphere L7 k=8 f64", flush=True)
+    m, K, M, b = _cfg2_system(7, 8, "f64")
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-8, max_iter=500)
+    assert rep["converged_all"], rep
+    assert max(rep["true_relres"]) <= 2e-8
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    uo, its, rr = oracle.pcg(rp, col, 1.0, M.cpu().numpy(), 1e-3, K.cpu().numpy(),
+                             b.cpu().numpy(), rtol=1e-8, max_iter=500)
+    assert all(abs(a - o) <= 1 for a, o in zip(rep["iters"], its)), (rep["iters"], its)
+    err = np.abs(u.cpu().numpy() - uo).max() / np.abs(uo).max()
+    assert err <= 1e-6, err
+
+
+def test_pcg_cfg2_f32_accuracy():
+    """FP32 storage, FP64 dots: solution within 1e-5 of the tight FP64 solution."""
+    print("[pcg] icosphere L6 k=8 f32", flush=True)
+    m64, K64, M64, b64 = _cfg2_system(6, 8, "f64")
+    m, K, M, b = _cfg2_system(6, 8, "f32")
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-8, max_iter=1000, stall_iters=20)
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    uo, _, _ = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3, K.double().cpu().numpy(),
+                          b.double().cpu().numpy(), rtol=1e-14, max_iter=5000)
+    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
+    assert err <= 1e-5, (err, rep)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pcg_dirichlet_cube(dtype):
+    print(f"[pcg-dirichlet] cube17 {dtype}", flush=True)
+    X, T = meshgen.cube_tets(17, 0.15, 0)
+    m = dgo.Mesh(torch.from_numpy(T).to(DEV), X.shape[0])
+    td = torch.float64 if dtype == "f64" else torch.float32
+    K, M = dgo.assemble(m, torch.from_numpy(X).to(DEV, td))
+    mask = m.boundary()
+    us = np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
+    g = torch.from_numpy(us).to(DEV, td)
+    b = (M * torch.from_numpy(3 * np.pi ** 2 * us).to(DEV, td)).contiguous()
+    rtol = 1e-10 if dtype == "f64" else 1e-6
+    u, rep = dgo.pcg(m, 0.0, M, 1.0, K, b, mask=mask, g=g, rtol=rtol, max_iter=3000,
+                     stall_iters=30 if dtype == "f32" else 0)
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    uo, its, _ = oracle.pcg(rp, col, 0.0, M.double().cpu().numpy(), 1.0, K.double().cpu().numpy(),
+                            b.double().cpu().numpy(), mask=mask.cpu().numpy(),
+                            g=g.double().cpu().numpy(), rtol=1e-14, max_iter=5000)
+    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
+    assert err <= (1e-8 if dtype == "f64" else 2e-4), (err, rep)
+    bm = mask.cpu().numpy() == 1
+    assert np.array_equal(u.double().cpu().numpy()[bm], g.double().cpu().numpy()[bm])
+
+
+def test_pcg_strict_and_deterministic():
+    m, K, M, b = _cfg2_system(4, 3, "f64")
+    with pytest.raises(dgo.DgoError) as e:
+        dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-12, max_iter=2, strict=True)
+    assert e.value.status == "NOT_CONVERGED"
+    u1, _ = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-10)
+    u2, _ = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-10)
+    assert torch.equal(u1, u2)
+    # a column solved alone agrees with the column solved in the block (the
+    # row split of the SpMV depends on k, so agreement is to rounding)
+    u0, _ = dgo.pcg(m, 1.0, M, 1e-3, K, b[:, 1].contiguous(), rtol=1e-10)
+    assert (u0 - u1[:, 1]).abs().max() <= 1e-9 * u1[:, 1].abs().max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_vjp_parity(dtype):
+    print(f"[vjp] ico5 {dtype}", flush=True)
+    X, F = meshgen.icosphere(5, 1e-2, 3)
+    m = dgo.Mesh(torch.from_numpy(F).to(DEV), X.shape[0])
+    td = torch.float64 if dtype == "f64" else torch.float32
+    Xd = torch.from_numpy(X).to(DEV, td)
+    gK = torch.from_numpy(meshgen.normal(11, m.nnz)).to(DEV, td)
+    gM = torch.from_numpy(meshgen.normal(12, m.nV)).to(DEV, td)
+    gX = dgo.assemble_vjp(m, Xd, gK, gM).double().cpu().numpy()
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    ref = oracle.assemble_vjp_tri(Xd.double().cpu().numpy(), F, rp, col,
+                                  gK.double().cpu().numpy(), gM.double().cpu().numpy())
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert np.abs(gX - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_autograd_loss_gradient_cfg5():
+    """loss = u^T K(x) u + total area through AssembleFn matches the oracle gradient."""
+    print("[autograd] batch of icosphere L5", flush=True)
+    B = 4
+    X0, F = meshgen.icosphere(5)
+    m = dgo.Mesh(torch.from_numpy(F).to(DEV), X0.shape[0])
+    Xs = np.stack([meshgen.icosphere(5, 1e-2, s)[0] for s in range(B)])
+    u = meshgen.normal(1000, X0.shape[0])
+    X = torch.from_numpy(Xs).to(DEV).requires_grad_(True)
+    K, M = dgo.AssembleFn.apply(X, m)
+    ud = torch.from_numpy(u).to(DEV)
+    rp, col = m.csr()
+    rows = torch.repeat_interleave(torch.arange(m.nV, device=DEV), (rp[1:] - rp[:-1]).long())
+    quad = (K * (ud[rows] * ud[col.long()])[None, :]).sum(1)
+    loss = (quad + M.sum(1)).sum()
+    loss.backward()
+    for b in range(B):
+        Lo, go = oracle.loss_grad_tri(Xs[b], F, u)
+        assert abs(float(quad[b] + M[b].sum()) - Lo) <= 1e-12 * abs(Lo)
+        g = X.grad[b].cpu().numpy()
+        assert np.abs(g - go).max() <= 1e-12 * np.abs(go).max()
