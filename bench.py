@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--kernel-reps", type=int, default=30)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--no-suite", action="store_true",
+                    help="skip the other workloads (tets, grid, VJP batch, size sweep)")
     return ap.parse_args()
 
 
@@ -54,14 +56,20 @@ def alg_bytes(kind, s, nV, nF, nnz, k):
     moved once (index arrays at 4 bytes, values at s bytes)."""
     if kind == "assemble_tri":
         return 3 * s * nV + 12 * nF + s * nnz + s * nV
+    if kind == "assemble_tet":
+        return 3 * s * nV + 16 * nF + s * nnz + s * nV
+    if kind == "assemble_vjp_tri":
+        # X, gK, gM read, gX written, triangles
+        return 3 * s * nV + 12 * nF + s * nnz + s * nV + 3 * s * nV
     if kind in ("spmm", "cg_spmm_dot"):
         # CSR values + columns, row pointers, mass diagonal, x read, y written
         return nnz * (s + 4) + 4 * (nV + 1) + s * nV + 2 * k * s * nV
     if kind == "cg_update":
-        # read x p r q, write x r z, read D^-1
-        return 7 * k * s * nV + s * nV
+        # read r q, write r, read D^-1
+        return 3 * k * s * nV + s * nV
     if kind == "cg_pupdate":
-        return 3 * k * s * nV
+        # read x p r, write x p, read D^-1
+        return 5 * k * s * nV + s * nV
     return None
 
 
@@ -221,10 +229,149 @@ def main():
         "baseline_note": PAPER_NOTE,
     }
 
+    if not args.no_suite:
+        out["suite"] = suite(args, dgo, torch, meshgen)
     if not args.no_cpu_baseline:
         log(args, "cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(X, F, f, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def kernel_time(dgo, torch, fn, name, reps, flush=None):
+    """Average duration (us) of the library kernel `name` over reps calls of fn,
+    from the library's hipEvents; with flush, 1 GiB is written before each."""
+    dgo.trace_reset()
+    dgo.trace_enable(True, name)
+    for _ in range(reps):
+        if flush is not None:
+            flush.zero_()
+        fn()
+    torch.cuda.synchronize()
+    dgo.trace_enable(False)
+    e = dgo.trace_read().get(name)
+    return None if e is None else e["total_ms"] / e["count"] * 1e3
+
+
+def roof(ab, us):
+    gbs = ab / (us * 1e-6) / 1e9
+    return {"us": us, "alg_bytes": ab, "gbps": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+
+def suite(args, dgo, torch, meshgen):
+    """The other workloads, each timed per kernel (warm and cache-flushed)."""
+    dev = torch.device("cuda:0")
+    reps = max(5, args.kernel_reps // 3)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    out = {}
+    td, s = (torch.float64, 8) if args.dtype == "f64" else (torch.float32, 4)
+
+    # tetrahedral volume: Kuhn cube 64^3, jitter 0.15 h, Dirichlet Poisson to 1e-8
+    log(args, "suite: Kuhn cube 64^3")
+    import numpy as np
+    X, T = meshgen.cube_tets(64, 0.15, 0)
+    m = dgo.Mesh(torch.from_numpy(T).to(dev), X.shape[0])
+    Xd = torch.from_numpy(X).to(dev, td)
+    K, M = dgo.assemble(m, Xd)
+    ent = {"nV": m.nV, "nT": m.n_elem, "nnz": m.nnz}
+    ab = alg_bytes("assemble_tet", s, m.nV, m.n_elem, m.nnz, 1)
+    for cold in (False, True):
+        us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xd, out=(K, M)), "assemble_tet", reps,
+                         flush if cold else None)
+        ent["assemble_" + ("cold" if cold else "warm")] = roof(ab, us)
+    ent["tets_per_s_cold"] = m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
+    x1 = torch.rand(m.nV, dtype=td, device=dev)
+    y1 = torch.empty_like(x1)
+    ab = alg_bytes("spmm", s, m.nV, m.n_elem, m.nnz, 1)
+    for cold in (False, True):
+        us = kernel_time(dgo, torch, lambda: dgo.spmv(m, 0.0, M, 1.0, K, x1, out=y1), "spmm", reps,
+                         flush if cold else None)
+        ent["spmv_k1_" + ("cold" if cold else "warm")] = roof(ab, us)
+    mask = m.boundary()
+    us_ = np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
+    g = torch.from_numpy(us_).to(dev, td)
+    b = (M * torch.from_numpy(3 * np.pi ** 2 * us_).to(dev, td)).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, rep = dgo.pcg(m, 0.0, M, 1.0, K, b, mask=mask, g=g, rtol=1e-8, max_iter=5000,
+                     check_every=16, stall_iters=50 if args.dtype == "f32" else 0)
+    torch.cuda.synchronize()
+    ent["dirichlet_pcg"] = {"ms": (time.perf_counter() - t0) * 1e3, "iters": rep["iters"][0],
+                            "true_relres": rep["true_relres"][0],
+                            "nodal_err_vs_exact": float((u - g).abs().max())}
+    out["cube64_tet"] = ent
+    del m, K, M, Xd
+
+    # plain method on the 64 x 64 grid: 100 SpMVs with K on a uniform[-1, 1] vector
+    log(args, "suite: grid 64x64")
+    X, F = meshgen.grid2d(64, 0.2, 0)
+    m = dgo.Mesh(torch.from_numpy(F).to(dev), X.shape[0])
+    Xd = torch.from_numpy(X).to(dev, td)
+    K, M = dgo.assemble(m, Xd)
+    x = torch.from_numpy(meshgen.uniform(1, m.nV) * 2 - 1).to(dev, td)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(100):
+        dgo.spmv(m, 0.0, M, 1.0, K, x, out=y)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e6 / 100
+    us = kernel_time(dgo, torch, lambda: dgo.spmv(m, 0.0, M, 1.0, K, x, out=y), "spmm", 100)
+    ua = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xd, out=(K, M)), "assemble_tri", 20)
+    out["grid64"] = {"spmv_us_kernel": us, "spmv_us_wall_per_call": wall, "assemble_us": ua,
+                     "note": "latency-bound size (0.4 MB per SpMV): reported in microseconds"}
+    del m
+
+    # differentiation batch: 256 icosphere L5 meshes, VJP of assembly
+    log(args, "suite: 256 x icosphere L5 VJP")
+    B = 256
+    X0, F = meshgen.icosphere(5)
+    m = dgo.Mesh(torch.from_numpy(F).to(dev), X0.shape[0])
+    Xs = np.stack([meshgen.icosphere(5, 1e-2, sd)[0] for sd in range(B)])
+    Xb = torch.from_numpy(Xs).to(dev, td)
+    Kb, Mb = dgo.assemble(m, Xb)
+    gK = torch.randn_like(Kb)
+    gM = torch.randn_like(Mb)
+    ent = {"batch": B, "nV": m.nV, "nF": m.n_elem}
+    ab = B * alg_bytes("assemble_tri", s, m.nV, m.n_elem, m.nnz, 1)
+    abv = B * alg_bytes("assemble_vjp_tri", s, m.nV, m.n_elem, m.nnz, 1)
+    for cold in (False, True):
+        tag = "cold" if cold else "warm"
+        us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xb, out=(Kb, Mb)), "assemble_tri",
+                         reps, flush if cold else None)
+        ent["assemble_" + tag] = roof(ab, us)
+        us = kernel_time(dgo, torch, lambda: dgo.assemble_vjp(m, Xb, gK, gM), "assemble_vjp_tri",
+                         reps, flush if cold else None)
+        ent["vjp_" + tag] = roof(abv, us)
+    ent["triangles_per_s_cold"] = B * m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
+    out["diff_batch_ico5"] = ent
+    del m, Xb, Kb, Mb, gK, gM
+
+    # size sweep past the 256 MB last-level cache: icosphere L8 and L9
+    for L in (8, 9):
+        log(args, f"suite: icosphere L{L}")
+        X, F = meshgen.icosphere(L, 1e-3, 0)
+        m = dgo.Mesh(torch.from_numpy(F).to(dev), X.shape[0])
+        Xd = torch.from_numpy(X).to(dev, td)
+        K, M = dgo.assemble(m, Xd)
+        xk = torch.randn(m.nV, 8, dtype=td, device=dev)
+        yk = torch.empty_like(xk)
+        ent = {"nV": m.nV, "nF": m.n_elem, "nnz": m.nnz}
+        ab = alg_bytes("assemble_tri", s, m.nV, m.n_elem, m.nnz, 8)
+        abs_ = alg_bytes("spmm", s, m.nV, m.n_elem, m.nnz, 8)
+        for cold in (False, True):
+            tag = "cold" if cold else "warm"
+            us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xd, out=(K, M)), "assemble_tri",
+                             reps, flush if cold else None)
+            ent["assemble_" + tag] = roof(ab, us)
+            us = kernel_time(dgo, torch, lambda: dgo.spmv(m, 1.0, M, 1e-3, K, xk, out=yk), "spmm",
+                             reps, flush if cold else None)
+            ent["spmv_k8_" + tag] = roof(abs_, us)
+        ent["triangles_per_s_cold"] = m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
+        out[f"icosphere_L{L}"] = ent
+        del m, K, M, Xd, xk, yk
+    del flush
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(X, F, f, budget_s):

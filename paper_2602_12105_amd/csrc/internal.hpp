@@ -103,13 +103,28 @@ struct dgo_mesh {
     int32_t rpb = 0;            // rows per workgroup
     int32_t nblocks = 0;        // ceil(nV / rpb)
     int32_t max_block_nnz = 0;  // largest CSR span of one block of rows
+    int32_t max_block_inc = 0;  // most incidence records of one block of rows
 
     // scratch workspace reused by numeric calls (grows on demand)
     void *ws = nullptr;
     size_t ws_bytes = 0;
+
+    // replayable graph of one chunk of solver iterations, valid for one exact
+    // set of launch arguments (key); replayed on a private stream joined to
+    // the caller's stream with events
+    hipGraphExec_t graph = nullptr;
+    uint64_t graph_key[24] = {};
+    hipStream_t graph_stream = nullptr;
+    hipEvent_t graph_ev[2] = {nullptr, nullptr};
 };
 
 namespace dgo {
+
+// True while kernel tracing is enabled (graphs are not used then).
+bool trace_active();
+
+// Release the cached graph of a mesh (if any).
+void mesh_drop_graph(dgo_mesh *m);
 
 // Grow the mesh workspace to at least `bytes`; contents are not preserved.
 dgo_status mesh_workspace(dgo_mesh *m, size_t bytes, hipStream_t s, void **out);
@@ -119,6 +134,21 @@ dgo_status mesh_workspace(dgo_mesh *m, size_t bytes, hipStream_t s, void **out);
 size_t scan_tmp_elems(int64_t n);
 dgo_status exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp,
                           hipStream_t s);
+
+// Row blocks of the assembly kernels: rows per workgroup (before halving to
+// fit the LDS budget) and the LDS a block needs: the block's CSR span
+// (values, column ids and the column vertices' positions), one record and CW
+// contributions per incidence, the block's own positions, and the block's row
+// and incidence offsets.
+constexpr int32_t kRowsPerBlockTri = 64;
+constexpr int32_t kRowsPerBlockTet = 16;
+constexpr int64_t kRowBlockLdsBytes = 64 * 1024;
+constexpr int kAssembleThreads = 256;
+
+inline int64_t assembly_lds_bytes(int dim, int s, int64_t rpb, int64_t span, int64_t ninc) {
+    const int cw = dim == 2 ? 3 : 4;
+    return span * (4 * s + 4) + ninc * (cw * s + 4) + rpb * 3 * s + 2 * (rpb + 1) * 4 + 64;
+}
 
 inline unsigned grid_for(int64_t n, int threads) {
     int64_t g = (n + threads - 1) / threads;

@@ -317,12 +317,14 @@ __global__ void k_count_mask(const uint8_t *mask, int32_t nV, int32_t *n) {
     if (v < nV && mask[v]) atomicAdd(n, 1);
 }
 
-__global__ void k_block_nnz(const int32_t *rowptr, int32_t nV, int32_t rpb, int32_t *mx) {
+__global__ void k_block_nnz(const int32_t *rowptr, const int32_t *vtptr, int32_t nV, int32_t rpb,
+                            int32_t *mx) {
     int32_t b = blockIdx.x * T + threadIdx.x;
     int64_t r0 = (int64_t)b * rpb;
     if (r0 >= nV) return;
     int64_t r1 = r0 + rpb < nV ? r0 + rpb : nV;
-    atomicMax(mx, rowptr[r1] - rowptr[r0]);
+    atomicMax(&mx[0], rowptr[r1] - rowptr[r0]);
+    atomicMax(&mx[1], vtptr[r1] - vtptr[r0]);
 }
 
 struct Tmp {
@@ -344,8 +346,6 @@ struct Tmp {
 
 }  // namespace
 
-// Largest LDS footprint a row block may need: column ids plus FP64 values.
-constexpr int32_t kRowBlockLdsBytes = 64 * 1024;
 
 static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
     const int dim = m->dim, nv = m->nv_elem, nl = m->nl;
@@ -480,16 +480,17 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
     }
     DGO_HIP(hipGetLastError());
 
-    // row blocks: the most rows per workgroup whose CSR span fits the LDS
-    int32_t rpb = dim == 2 ? 256 : 128;
+    // row blocks: the most rows per workgroup whose CSR span and incidence
+    // records fit the LDS budget of the assembly kernels
+    int32_t rpb = dim == 2 ? kRowsPerBlockTri : kRowsPerBlockTet;
     for (;;) {
-        DGO_HIP(hipMemsetAsync(flags + 5, 0, sizeof(int32_t), s));
+        DGO_HIP(hipMemsetAsync(flags + 5, 0, 2 * sizeof(int32_t), s));
         int32_t nb = (int32_t)((nV + rpb - 1) / rpb);
-        if (nb) k_block_nnz<<<grid_for(nb, T), T, 0, s>>>(m->rowptr, nV, rpb, flags + 5);
+        if (nb) k_block_nnz<<<grid_for(nb, T), T, 0, s>>>(m->rowptr, m->vtptr, nV, rpb, flags + 5);
         DGO_HIP(hipGetLastError());
         DGO_HIP(hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s));
         DGO_HIP(hipStreamSynchronize(s));
-        if ((int64_t)hf[5] * 12 <= kRowBlockLdsBytes || rpb <= 16) break;
+        if (assembly_lds_bytes(dim, 8, rpb, hf[5], hf[6]) <= kRowBlockLdsBytes || rpb <= 1) break;
         rpb /= 2;
     }
     m->n_bfaces = hf[2];
@@ -498,14 +499,21 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
     m->rpb = rpb;
     m->nblocks = (int32_t)((nV + rpb - 1) / rpb);
     m->max_block_nnz = hf[5];
+    m->max_block_inc = hf[6];
     if (m->max_row > 255)
         return fail(DGO_ERR_UNSUPPORTED, "mesh: a vertex has more than 254 neighbours");
-    if ((int64_t)m->max_block_nnz * 12 > kRowBlockLdsBytes)
-        return fail(DGO_ERR_UNSUPPORTED, "mesh: row block exceeds the LDS budget");
+    if (assembly_lds_bytes(dim, 8, rpb, hf[5], hf[6]) > kRowBlockLdsBytes)
+        return fail(DGO_ERR_UNSUPPORTED, "mesh: a vertex's row exceeds the LDS budget");
     return DGO_OK;
 }
 
 static void release(dgo_mesh *m, hipStream_t s) {
+    mesh_drop_graph(m);
+    if (m->graph_ev[0]) (void)hipEventDestroy(m->graph_ev[0]);
+    if (m->graph_ev[1]) (void)hipEventDestroy(m->graph_ev[1]);
+    if (m->graph_stream) (void)hipStreamDestroy(m->graph_stream);
+    m->graph_ev[0] = m->graph_ev[1] = nullptr;
+    m->graph_stream = nullptr;
     void *ptrs[] = {m->elem, m->EV, m->elem_edge, m->elem_sign, m->rowptr, m->col,
                     m->diag, m->vtptr, m->inc, m->bmask, m->ws};
     for (void *p : ptrs) m->alloc.put(p, s);

@@ -87,6 +87,8 @@ TraceScope::~TraceScope() {
     if (g_pending.size() > 4096) resolve_locked();
 }
 
+bool trace_active() { return g_on.load(std::memory_order_relaxed); }
+
 }  // namespace dgo
 
 using namespace dgo;
