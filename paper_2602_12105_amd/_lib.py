@@ -44,14 +44,14 @@ class CgReport(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("dtype", i32), ("max_slots", i32), ("hbm_budget_bytes", i64),
-                ("cg_iters", i32), ("cg_chunk", i32), ("alpha", f64), ("beta", f64),
-                ("max_batch_rows", i64), ("batched", i32), ("pad", i32)]
+    _fields_ = [("max_slots", i32), ("cg_iters", i32), ("cg_chunk", i32), ("batched", i32),
+                ("hbm_budget_bytes", i64), ("alpha", f64), ("beta", f64),
+                ("prep_threads", i32), ("pad", i32)]
 
 
 class Request(C.Structure):
-    _fields_ = [("dim", i32), ("nV", i32), ("n_elem", i64), ("k", i32), ("pad", i32),
-                ("h_elem", P), ("h_X", P), ("h_b", P), ("h_u", P), ("user", C.c_uint64)]
+    _fields_ = [("nV", i32), ("k", i32), ("nF", i64), ("h_F", P), ("h_X", P), ("h_f", P),
+                ("h_u", P), ("user", C.c_uint64)]
 
 
 class ReqStats(C.Structure):
@@ -60,10 +60,11 @@ class ReqStats(C.Structure):
                 ("footprint", i64)]
 
 
-class ServerStats(C.Structure):
+class ServerCounters(C.Structure):
     _fields_ = [("submitted", i64), ("admitted", i64), ("completed", i64), ("rejected", i64),
                 ("failed", i64), ("queue_depth", i64), ("active", i64), ("hbm_in_use", i64),
-                ("hbm_peak", i64), ("ticks", i64), ("batched_launches", i64), ("busy_s", f64)]
+                ("hbm_peak", i64), ("ticks", i64), ("max_batch", i64), ("busy_s", f64),
+                ("now_s", f64)]
 
 
 class TraceEntry(C.Structure):
@@ -95,7 +96,8 @@ SERVER_SIGNATURES = {
     "dgo_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(P)]),
     "dgo_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
     "dgo_server_wait": (C.c_int, [P, C.c_uint64, f64, C.POINTER(ReqStats)]),
-    "dgo_server_stats": (C.c_int, [P, C.POINTER(ServerStats)]),
+    "dgo_server_stats": (C.c_int, [P, C.POINTER(ServerCounters)]),
+    "dgo_server_footprint": (i64, [i32, i64, i32]),
     "dgo_server_destroy": (None, [P]),
 }
 

@@ -1,0 +1,512 @@
+// Device code shared by the per-mesh kernels and the batched serving kernels:
+// geometry helpers, the assembly of one row block, the SpMM row core, and the
+// reduction and state-update pieces of PCG.
+#pragma once
+
+#include "internal.hpp"
+
+namespace dgo {
+namespace kern {
+
+constexpr int T = 256;
+constexpr int kMaxK = 64;
+constexpr int kMaxBlocks = 4096; // workgroups of a streaming kernel
+constexpr int kMaxRedBlocks = 1024; // workgroups of a kernel that stores partial sums
+constexpr int kFinThreads = 1024;
+constexpr int kVecUnroll = 1;     // rows per thread per step in the vector kernels (measured best)
+
+struct CgCol {
+    double rz, pq, alpha, beta, rr, bb, best;
+    int32_t iters, since, active, converged;
+    int32_t stalled, pad0;
+};
+
+struct CgParams {
+    double rtol;
+    int32_t max_iter, fixed, stall;
+    int32_t k;
+};
+
+
+
+inline int pow2ceil(int k) {
+    int G = 1;
+    while (G < k) G *= 2;
+    return G;
+}
+
+template <typename R>
+struct V3 {
+    R x, y, z;
+};
+
+template <typename R>
+__device__ __forceinline__ V3<R> ld3(const R *X, int32_t v) {
+    const R *p = X + 3 * (int64_t)v;
+    return {p[0], p[1], p[2]};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> sub(V3<R> a, V3<R> b) {
+    return {a.x - b.x, a.y - b.y, a.z - b.z};
+}
+template <typename R>
+__device__ __forceinline__ R dot(V3<R> a, V3<R> b) {
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename R>
+__device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> axpy(R s, V3<R> a, V3<R> b) {  // s a + b
+    return {s * a.x + b.x, s * a.y + b.y, s * a.z + b.z};
+}
+
+// cot of the angle at xk between (xp - xk) and (xq - xk); callers pass the
+// edge endpoints (p, q) sorted by vertex id.
+template <typename R>
+__device__ __forceinline__ R cot_at(V3<R> xp, V3<R> xq, V3<R> xk) {
+    V3<R> e1 = sub(xp, xk), e2 = sub(xq, xk);
+    V3<R> n = cross(e1, e2);
+    return dot(e1, e2) / sqrt(dot(n, n));
+}
+
+template <typename R>
+__device__ __forceinline__ R clamp_w(R w, int use_clamp, R cmin) {
+    return (use_clamp && w < cmin) ? cmin : w;
+}
+
+
+// P1 stiffness of one tetrahedron in its own vertex order: the rows of E^{-1},
+// E = [x1 - x0, x2 - x0, x3 - x0] (as columns), are the gradients of the
+// barycentric functions 1..3: grad phi_1 = (e2 x e3)/det, grad phi_2 =
+// (e3 x e1)/det, grad phi_3 = (e1 x e2)/det, grad phi_0 = -(sum).
+template <typename R>
+struct TetG {
+    V3<R> g0, g1, g2, g3;
+    R vol, det;
+};
+
+template <typename R>
+__device__ __forceinline__ TetG<R> tet_grads(V3<R> x0, V3<R> x1, V3<R> x2, V3<R> x3) {
+    const V3<R> e1 = sub(x1, x0), e2 = sub(x2, x0), e3 = sub(x3, x0);
+    const V3<R> c23 = cross(e2, e3), c31 = cross(e3, e1), c12 = cross(e1, e2);
+    TetG<R> t;
+    t.det = dot(e1, c23);
+    const R inv = R(1) / t.det;
+    t.g1 = {c23.x * inv, c23.y * inv, c23.z * inv};
+    t.g2 = {c31.x * inv, c31.y * inv, c31.z * inv};
+    t.g3 = {c12.x * inv, c12.y * inv, c12.z * inv};
+    t.g0 = {-(t.g1.x + t.g2.x + t.g3.x), -(t.g1.y + t.g2.y + t.g3.y),
+            -(t.g1.z + t.g2.z + t.g3.z)};
+    t.vol = fabs(t.det) / R(6);
+    return t;
+}
+
+// One of four scalars by index, as a chain of conditional moves.
+template <typename R>
+__device__ __forceinline__ R sel4(int p, R a, R b, R c, R d) {
+    R r = a;
+    r = p == 1 ? b : r;
+    r = p == 2 ? c : r;
+    r = p == 3 ? d : r;
+    return r;
+}
+
+template <typename R>
+__device__ __forceinline__ V3<R> sel2v(bool c, V3<R> a, V3<R> b) {
+    return {c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
+}
+
+// LDS layout of the assembly kernels for one block of rows [r0, r1). Arrays
+// of records are stored field-major (structure of arrays) so that lanes
+// touching consecutive entries hit consecutive banks:
+//   acc  : R[span]          the block's CSR values (accumulated, then finished)
+//   cw   : R[CW][inc_max]   per-incidence contributions (phase A)
+//   xl   : R[3][span_max]   positions of the column vertex of each CSR entry
+//   xo   : R[3][rpb]        positions of the block's own vertices
+//   lcol : int32[span]      the block's column ids
+//   lrec : uint32[ninc]     the block's incidence records
+//   lrp  : int32[rpb + 1]   row offsets into the span
+//   lvt  : int32[rpb + 1]   row offsets into the incidence records
+// Every position an element needs is a column of the row it is accumulated
+// into, so phase A reads positions from LDS only: X is gathered once per CSR
+// entry of the block (coalesced in the CSR order) instead of three times per
+// incidence.
+template <typename R, int CW>
+struct BlockLds {
+    R *acc, *cw, *xl, *xo;
+    int32_t *lcol, *lrp, *lvt;
+    uint32_t *lrec;
+    int32_t inc_max, span_max, rpb;
+    __device__ BlockLds(unsigned char *smem, int32_t span_max_, int32_t inc_max_, int32_t rpb_)
+        : inc_max(inc_max_), span_max(span_max_), rpb(rpb_) {
+        acc = (R *)smem;
+        cw = acc + span_max;
+        xl = cw + (size_t)inc_max * CW;
+        xo = xl + (size_t)span_max * 3;
+        lcol = (int32_t *)(xo + (size_t)rpb * 3);
+        lrec = (uint32_t *)(lcol + span_max);
+        lrp = (int32_t *)(lrec + inc_max);
+        lvt = lrp + rpb + 1;
+    }
+    __device__ R &c(int f, int32_t q) { return cw[(size_t)f * inc_max + q]; }
+    __device__ V3<R> pos(int32_t j) const {
+        return {xl[j], xl[span_max + j], xl[2 * span_max + j]};
+    }
+    __device__ V3<R> own(int32_t r) const { return {xo[r], xo[rpb + r], xo[2 * rpb + r]}; }
+};
+
+// Row of incidence q within the block: the r with lvt[r] <= q < lvt[r + 1].
+__device__ __forceinline__ int32_t row_of(const int32_t *lvt, int32_t nrows, int32_t q) {
+    int32_t lo = 0, hi = nrows;  // invariant: lvt[lo] <= q < lvt[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (lvt[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Phase A runs one thread per (vertex, element) incidence of the block and
+// stores the element's terms for that vertex's row; phase B runs one thread
+// per row and adds them in incidence (ascending element) order.
+// Topology a row block needs (the mesh's CSR pattern and incidence records).
+struct AsmView {
+    const int32_t *rowptr, *col, *vtptr;
+    const uint32_t *inc;
+    int32_t nV, rpb, span_max, inc_max;
+};
+
+// Assemble the row block `tile` of one mesh into Kvals / Mdiag (called by the
+// whole workgroup; smem holds assembly_lds_bytes of the view).
+template <typename R, int DIM>
+__device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restrict__ X,
+                               R *__restrict__ Kvals, R *__restrict__ Mdiag, int use_clamp,
+                               R cmin, int32_t *__restrict__ n_degenerate, unsigned char *smem) {
+    constexpr int CW = DIM == 2 ? 3 : 4;
+    const int32_t *__restrict__ rowptr = v.rowptr;
+    const int32_t *__restrict__ col = v.col;
+    const int32_t *__restrict__ vtptr = v.vtptr;
+    const uint32_t *__restrict__ inc = v.inc;
+    const int32_t nV = v.nV, rpb = v.rpb, span_max = v.span_max;
+    BlockLds<R, CW> L(smem, span_max, v.inc_max, rpb);
+    const int32_t r0 = (int32_t)tile * rpb;
+    const int32_t r1 = min(r0 + rpb, nV), nrows = r1 - r0;
+    const int32_t s0 = rowptr[r0], span = rowptr[r1] - s0;
+    const int32_t q0 = vtptr[r0], ninc = vtptr[r1] - q0;
+    const int t = threadIdx.x;
+    for (int32_t j = t; j <= nrows; j += blockDim.x) {
+        L.lrp[j] = rowptr[r0 + j] - s0;
+        L.lvt[j] = vtptr[r0 + j] - q0;
+    }
+    for (int32_t j = t; j < 3 * nrows; j += blockDim.x) {
+        const int32_t r = j / 3, c = j - 3 * r;
+        L.xo[c * rpb + r] = X[3 * (int64_t)r0 + j];
+    }
+    for (int32_t j = t; j < span; j += blockDim.x) {
+        const int32_t c = col[s0 + j];
+        L.lcol[j] = c;
+        L.acc[j] = R(0);
+        L.xl[j] = X[3 * (int64_t)c];
+        L.xl[span_max + j] = X[3 * (int64_t)c + 1];
+        L.xl[2 * span_max + j] = X[3 * (int64_t)c + 2];
+    }
+    for (int32_t q = t; q < ninc; q += blockDim.x) L.lrec[q] = inc[q0 + q];
+    __syncthreads();
+    int ndeg = 0;
+    // phase A: element terms per incidence, from LDS only
+    for (int32_t q = t; q < ninc; q += blockDim.x) {
+        const uint32_t rec = L.lrec[q];
+        const int32_t rr = row_of(L.lvt, nrows, q);
+        const int32_t i = r0 + rr, base = L.lrp[rr];
+        const int32_t la = base + (int32_t)(rec & 255u), lb = base + (int32_t)((rec >> 8) & 255u);
+        const V3<R> xi = L.own(rr);
+        if (DIM == 2) {
+            const int32_t a = L.lcol[la], b = L.lcol[lb];
+            const V3<R> xa = L.pos(la), xb = L.pos(lb);
+            // edge (i, a) is opposite b and edge (i, b) is opposite a; the
+            // endpoints go in vertex-id order so both rows compute the same value
+            const R cb = i < a ? cot_at(xi, xa, xb) : cot_at(xa, xi, xb);
+            const R ca = i < b ? cot_at(xi, xb, xa) : cot_at(xb, xi, xa);
+            const V3<R> n = cross(sub(xa, xi), sub(xb, xi));
+            const R n2 = dot(n, n);
+            L.c(0, q) = R(0.5) * cb;
+            L.c(1, q) = R(0.5) * ca;
+            L.c(2, q) = R(0.5) * sqrt(n2) / R(3);
+            if (n2 == R(0) && i < a && i < b) ++ndeg;
+        } else {
+            const int p = (int)(rec >> 24);
+            const int32_t lc = base + (int32_t)((rec >> 16) & 255u);
+            const int32_t w0 = L.lcol[la], w1 = L.lcol[lb], w2 = L.lcol[lc];
+            const V3<R> y0 = L.pos(la), y1 = L.pos(lb), y2 = L.pos(lc);
+            // element order: i sits at position p, the others follow in order
+            const V3<R> x0 = sel2v(p == 0, xi, y0);
+            const V3<R> x1 = sel2v(p == 0, y0, sel2v(p == 1, xi, y1));
+            const V3<R> x2 = sel2v(p <= 1, y1, sel2v(p == 2, xi, y2));
+            const V3<R> x3 = sel2v(p <= 2, y2, xi);
+            const TetG<R> tg = tet_grads(x0, x1, x2, x3);
+            // every pair's product in one fixed operand order, then the three
+            // pairs (p, other) in element order
+            const R d01 = dot(tg.g0, tg.g1), d02 = dot(tg.g0, tg.g2), d03 = dot(tg.g0, tg.g3);
+            const R d12 = dot(tg.g1, tg.g2), d13 = dot(tg.g1, tg.g3), d23 = dot(tg.g2, tg.g3);
+            L.c(0, q) = -(tg.vol * sel4(p, d01, d01, d02, d03));
+            L.c(1, q) = -(tg.vol * sel4(p, d02, d12, d12, d13));
+            L.c(2, q) = -(tg.vol * sel4(p, d03, d13, d23, d23));
+            L.c(3, q) = tg.vol / R(4);
+            if (tg.det == R(0) && i < w0 && i < w1 && i < w2) ++ndeg;
+        }
+    }
+    if (ndeg) atomicAdd(n_degenerate, ndeg);
+    __syncthreads();
+    // phase B: one thread per row adds the row's incidence terms in incidence
+    // (ascending element) order, then forms the diagonal (the sum of the
+    // row's weights in column order), negates the off-diagonals and stores
+    // the lumped mass
+    for (int32_t rr = t; rr < nrows; rr += blockDim.x) {
+        const int32_t base = L.lrp[rr], len = L.lrp[rr + 1] - base, i = r0 + rr;
+        R m = 0;
+        for (int32_t q = L.lvt[rr]; q < L.lvt[rr + 1]; ++q) {
+            const uint32_t rec = L.lrec[q];
+            L.acc[base + (rec & 255u)] += L.c(0, q);
+            L.acc[base + ((rec >> 8) & 255u)] += L.c(1, q);
+            if (DIM == 3) L.acc[base + ((rec >> 16) & 255u)] += L.c(2, q);
+            m += L.c(CW - 1, q);
+        }
+        R sum = 0;
+        int32_t dslot = 0;
+        for (int32_t u = 0; u < len; ++u) {
+            if (L.lcol[base + u] == i) {
+                dslot = u;
+                continue;
+            }
+            const R w = clamp_w(L.acc[base + u], use_clamp, cmin);
+            sum += w;
+            L.acc[base + u] = -w;
+        }
+        L.acc[base + dslot] = sum;
+        Mdiag[i] = m;
+    }
+    __syncthreads();
+    for (int32_t j = t; j < span; j += blockDim.x) Kvals[s0 + j] = L.acc[j];
+    __syncthreads();
+}
+
+// Contiguous chunk of tiles for this workgroup; each XCD's workgroups cover
+// one contiguous range of tiles, so neighbouring rows share an L2.
+__device__ __forceinline__ void tile_range(int64_t ntiles, int64_t &t0, int64_t &t1) {
+    const uint32_t nb = gridDim.x;
+    const uint32_t lb = xcd_tile(blockIdx.x, nb);
+    const int64_t per = (ntiles + nb - 1) / nb;
+    t0 = (int64_t)lb * per;
+    t1 = t0 + per < ntiles ? t0 + per : ntiles;
+}
+
+// ------------------------------------------------------ fixed-order reduce
+
+// Store the workgroup's W partial sums (LDS) column-major, at
+// part[w * gridDim.x + blockIdx.x], so that the finalize kernel reads each
+// value's partials as one contiguous run.
+__device__ __forceinline__ void store_partials(const double *s_part, int W, double *part) {
+    if ((int)threadIdx.x < W) part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s_part[threadIdx.x];
+}
+
+// tot[w] = sum over b < nblk of part[w * nblk + b] in a fixed order, computed by
+// one workgroup of kFinThreads threads: thread t sums the strided subset
+// b = t % tpw (mod tpw) of value w = t / tpw (loads issued kFinUnroll at a
+// time, added in order), then thread w adds its tpw subtotals in order.
+constexpr int kFinUnroll = 16;
+
+__device__ void fin_sum(const double *__restrict__ part, int nblk, int W, double *scr,
+                        double *tot) {
+    const int t = threadIdx.x;
+    const int tpw = kFinThreads / W;
+    const int w = t / tpw, sub = t % tpw;
+    double s = 0.0;
+    if (w < W) {
+        for (int b0 = sub; b0 < nblk; b0 += tpw * kFinUnroll) {
+            double v[kFinUnroll];
+#pragma unroll
+            for (int u = 0; u < kFinUnroll; ++u) {
+                const int b = b0 + u * tpw;
+                v[u] = b < nblk ? part[(size_t)w * nblk + b] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kFinUnroll; ++u) s += v[u];
+        }
+    }
+    scr[t] = s;
+    __syncthreads();
+    if (t < W) {
+        double a = 0.0;
+        for (int j = 0; j < tpw; ++j) a += scr[t * tpw + j];
+        tot[t] = a;
+    }
+    __syncthreads();
+}
+
+// Per-column workgroup partials of per-lane values: column c lives in lanes
+// whose index within their group of G lanes is c.
+__device__ __forceinline__ void column_partials(const double *vals, int nval, int k, int G,
+                                                bool act, double *s_red, double *s_part) {
+    for (int v = 0; v < nval; ++v) {
+        __syncthreads();
+        s_red[threadIdx.x] = act ? vals[v] : 0.0;
+        __syncthreads();
+        if ((int)threadIdx.x < k) {
+            double a = 0.0;
+            for (int t = threadIdx.x; t < T; t += G) a += s_red[t];
+            s_part[v * k + threadIdx.x] = a;
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ SpMM
+
+// RU rows of (alpha M + beta K) x for the calling group of G lanes, all
+// loads of the RU rows issued together. ok[u] = false rows yield 0. The
+// results are meaningful in lanes lane < KP with lane < k.
+template <typename R, int G, int KP, bool MASK, int RU>
+__device__ __forceinline__ void rows_core(const int32_t *__restrict__ rowptr,
+                                          const int32_t *__restrict__ col,
+                                          const R *__restrict__ K, const R *__restrict__ M,
+                                          R alpha, R beta, const uint8_t *__restrict__ mask,
+                                          const R *__restrict__ x, const int32_t (&i)[RU],
+                                          const bool (&ok)[RU], int k, int lane, int gbase,
+                                          R (&acc)[RU]) {
+    constexpr int NP = G / KP;
+    const int c = lane % KP, part = lane / KP;
+    const int cc = c < k ? c : k - 1;
+    int32_t rb[RU], re[RU];
+    R dterm[RU];
+    int32_t len = 0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        rb[u] = ok[u] ? rowptr[i[u]] : 0;
+        re[u] = ok[u] ? rowptr[i[u] + 1] : 0;
+        dterm[u] = ok[u] ? alpha * M[i[u]] : R(0);
+        len = max(len, re[u] - rb[u]);
+        acc[u] = 0;
+    }
+    for (int32_t e0 = 0; e0 < len; e0 += G) {
+        int32_t cj[RU];
+        R aj[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int32_t e = rb[u] + e0 + lane;
+            cj[u] = 0;
+            aj[u] = 0;
+            if (e < re[u]) {
+                const int32_t j = col[e];
+                if (!MASK || !mask[j]) {
+                    cj[u] = j;
+                    aj[u] = beta * K[e];
+                    if (j == i[u]) aj[u] += dterm[u];
+                }
+            }
+        }
+        if (KP == 1) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u) acc[u] += aj[u] * x[cj[u]];
+        } else {
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+#pragma unroll
+                for (int s = 0; s < KP; ++s) {
+                    const int t = s * NP + part;
+                    const int32_t j = __shfl(cj[u], gbase + t);
+                    const R a = __shfl(aj[u], gbase + t);
+                    acc[u] += a * x[(int64_t)j * k + cc];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+#pragma unroll
+        for (int off = G / 2; off >= KP; off /= 2) acc[u] += __shfl_down(acc[u], off, G);
+    }
+}
+
+// Rows handled together by one lane group.
+constexpr int kRowsInFlight = 1;
+
+// Lane layout of the vector kernels: KP lanes per row, lane c owns column c.
+struct VLane {
+    int c;
+    bool act;
+    int grp, gpb;
+};
+
+__device__ __forceinline__ VLane vlane(int k, int KP) {
+    VLane v;
+    v.c = threadIdx.x % KP;
+    v.act = v.c < k;
+    v.grp = threadIdx.x / KP;
+    v.gpb = T / KP;
+    return v;
+}
+
+
+enum FinMode { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUT = 3 };
+
+__host__ __device__ inline int fin_width(int mode, int k) {
+    return (mode == FIN_INIT ? 3 : (mode == FIN_BETA ? 2 : 1)) * k;
+}
+
+// Per-column PCG state transitions from the reduced dots `tot` (layout as
+// stored by the kernel that produced them):
+//   FIN_INIT : tot = [r.z | r.r | b.b]   (start; stop at once if already small)
+//   FIN_ALPHA: tot = [p.q]               alpha = rz / pq for active columns
+//   FIN_BETA : tot = [r.z | r.r]         beta, iteration count, stopping tests
+__device__ inline void cg_state_update(int mode, CgCol &s, const double *tot, int c, int k,
+                                       const CgParams &prm) {
+    if (mode == FIN_INIT) {
+        s.rz = tot[c];
+        s.rr = tot[k + c];
+        s.bb = tot[2 * k + c];
+        s.best = s.rr;
+        s.iters = 0;
+        s.since = 0;
+        s.stalled = 0;
+        s.pq = 0.0;
+        s.alpha = 0.0;
+        s.beta = 0.0;
+        const bool conv = !prm.fixed && sqrt(s.rr) <= prm.rtol * sqrt(s.bb);
+        s.converged = conv ? 1 : 0;
+        s.active = (!conv && prm.max_iter > 0) ? 1 : 0;
+    } else if (mode == FIN_ALPHA) {
+        const double pq = tot[c];
+        s.pq = pq;
+        s.alpha = (s.active && pq != 0.0) ? s.rz / pq : 0.0;
+    } else if (mode == FIN_BETA && s.active) {
+        const double rz_new = tot[c], rr = tot[k + c];
+        s.beta = s.rz != 0.0 ? rz_new / s.rz : 0.0;
+        s.rz = rz_new;
+        s.rr = rr;
+        s.iters += 1;
+        if (rr < s.best) {
+            s.best = rr;
+            s.since = 0;
+        } else {
+            s.since += 1;
+        }
+        if (!prm.fixed && sqrt(rr) <= prm.rtol * sqrt(s.bb)) {
+            s.converged = 1;
+            s.active = 0;
+        } else if (s.iters >= prm.max_iter) {
+            s.active = 0;
+        } else if (!prm.fixed && prm.stall > 0 && s.since >= prm.stall) {
+            s.stalled = 1;
+            s.active = 0;
+        }
+    }
+}
+
+}  // namespace kern
+
+inline kern::AsmView view_of(const dgo_mesh *m) {
+    return {m->rowptr, m->col, m->vtptr, m->inc, m->nV, m->rpb, m->max_block_nnz, m->max_block_inc};
+}
+
+}  // namespace dgo

@@ -1,0 +1,582 @@
+// Serving loop on the GPU: the executor behind the scheduler core, its
+// batched kernels, and the dgo_server_* C entry points.
+//
+// Batched execution. Every active request is described by a SrvDesc (its
+// topology, its device arrays and this tick's plan) in one device array that
+// is rewritten before each tick. The kernels are persistent: a fixed grid
+// walks the concatenated row tiles of all active requests, looks up the
+// request a tile belongs to by binary search over the requests' tile
+// offsets, and runs that request's tile with the same per-tile code as the
+// per-mesh kernels. One tick is: assembly and solver start for requests that
+// joined, then `cg_chunk` PCG iterations (SpMM with p.q, finalize alpha,
+// residual update with r.z and r.r, finalize beta, x and p update) for every
+// request that still has iterations left. The launch sequence of a tick never
+// changes, so it is captured once as a graph and replayed every tick.
+//
+// A request's tiles, partial sums and reduction order depend only on the
+// request, so its result is bitwise the same alone or in any batch.
+#include <cstring>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "../../include/dgo_serve.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+#include "serve_core.hpp"
+
+namespace dgo {
+namespace {
+
+using namespace kern;
+using R = float;
+
+constexpr int kSrvBlocks = 2048;      // persistent grid of the batched streaming kernels
+constexpr int kSrvAsmBlocks = 1024;   // persistent grid of the batched assembly
+constexpr int kSrvMaxSlots = 256;
+constexpr int kSrvMaxK = 16;
+
+struct SrvDesc {
+    AsmView view;
+    const int32_t *diag;
+    int64_t nnz;
+    const R *X, *f;
+    R *K, *M, *u, *r, *p, *q, *invD;
+    double *part;
+    CgCol *st;
+    int32_t k, KP, init, iters;
+    int32_t tiles_s, tiles_v, off_a, off_s, off_v, nblocks;
+};
+
+struct SrvHdr {
+    int32_t n, tot_a, tot_s, tot_v;
+};
+
+enum Space { SP_A = 0, SP_S = 1, SP_V = 2 };
+
+__device__ __forceinline__ int32_t off_of(const SrvDesc &d, int sp) {
+    return sp == SP_A ? d.off_a : (sp == SP_S ? d.off_s : d.off_v);
+}
+
+// The request owning global tile v: the last r with off(r) <= v (requests
+// with no tiles share their offset with the next one and are skipped).
+__device__ __forceinline__ int find_req(const SrvDesc *d, int n, int32_t v, int sp) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off_of(d[mid], sp) <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kAssembleThreads)
+ks_assemble(const SrvHdr *hdr, const SrvDesc *d, int32_t *ndeg) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = hdr->n, tot = hdr->tot_a;
+    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
+        const SrvDesc &q = d[find_req(d, n, v, SP_A)];
+        assemble_block<R, 2>(q.view, (uint32_t)(v - q.off_a), q.X, q.K, q.M, 0, R(0), ndeg, smem);
+    }
+}
+
+// Start of the solve (x0 = 0): D^-1, b = M f, r = b, p = D^-1 r; partial sums
+// of r.z, r.r, b.b.
+__global__ void __launch_bounds__(T)
+ks_init(const SrvHdr *hdr, const SrvDesc *d, R alpha, R beta) {
+    __shared__ double s_part[3 * kSrvMaxK];
+    __shared__ double s_red[T];
+    const int n = hdr->n, tot = hdr->tot_v;
+    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
+        const SrvDesc &q = d[find_req(d, n, v, SP_V)];
+        if (!q.init) continue;
+        const int32_t tile = v - q.off_v;
+        const VLane L = vlane(q.k, q.KP);
+        const int64_t i = (int64_t)tile * L.gpb + L.grp;
+        const bool on = L.act && i < q.view.nV;
+        double dd[3] = {0.0, 0.0, 0.0};
+        if (on) {
+            const R inv = R(1) / (alpha * q.M[i] + beta * q.K[q.diag[i]]);
+            if (L.c == 0) q.invD[i] = inv;
+            const int64_t e = i * q.k + L.c;
+            const R b = q.M[i] * q.f[e];
+            const R z = inv * b;
+            q.u[e] = R(0);
+            q.r[e] = b;
+            q.p[e] = z;
+            dd[0] = (double)b * (double)z;
+            dd[1] = (double)b * (double)b;
+            dd[2] = dd[1];
+        }
+        column_partials(dd, 3, q.k, q.KP, on, s_red, s_part);
+        const int W = 3 * q.k;
+        if ((int)threadIdx.x < W) q.part[(size_t)threadIdx.x * q.tiles_v + tile] = s_part[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+template <int KP>
+__device__ __forceinline__ void spmm_tile(const SrvDesc &q, int32_t tile, R alpha, R beta,
+                                          double *s_red, double *s_part) {
+    constexpr int G = KP < 8 ? 8 : KP;
+    constexpr int GPB = T / G;
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int gbase = (threadIdx.x & 63) - lane;
+    const int32_t row = tile * GPB + grp;
+    const int32_t i[1] = {row < q.view.nV ? row : 0};
+    const bool ok[1] = {row < q.view.nV};
+    R acc[1];
+    rows_core<R, G, KP, false, 1>(q.view.rowptr, q.view.col, q.K, q.M, alpha, beta, nullptr, q.p, i,
+                                  ok, q.k, lane, gbase, acc);
+    const bool out = ok[0] && lane < q.k && lane < KP;
+    double ds = 0.0;
+    if (out) {
+        const int64_t e = (int64_t)row * q.k + lane;
+        q.q[e] = acc[0];
+        ds = (double)q.p[e] * (double)acc[0];
+    }
+    column_partials(&ds, 1, q.k, G, out, s_red, s_part);
+    if ((int)threadIdx.x < q.k) q.part[(size_t)threadIdx.x * q.tiles_s + tile] = s_part[threadIdx.x];
+    __syncthreads();
+}
+
+// q = A p with the partial sums of p.q, iteration j of the tick.
+__global__ void __launch_bounds__(T)
+ks_spmm(const SrvHdr *hdr, const SrvDesc *d, int j, R alpha, R beta) {
+    __shared__ double s_part[kSrvMaxK];
+    __shared__ double s_red[T];
+    const int n = hdr->n, tot = hdr->tot_s;
+    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
+        const SrvDesc &q = d[find_req(d, n, v, SP_S)];
+        if (j >= q.iters) continue;
+        const int32_t tile = v - q.off_s;
+        switch (q.KP) {
+            case 1: spmm_tile<1>(q, tile, alpha, beta, s_red, s_part); break;
+            case 2: spmm_tile<2>(q, tile, alpha, beta, s_red, s_part); break;
+            case 4: spmm_tile<4>(q, tile, alpha, beta, s_red, s_part); break;
+            case 8: spmm_tile<8>(q, tile, alpha, beta, s_red, s_part); break;
+            default: spmm_tile<16>(q, tile, alpha, beta, s_red, s_part); break;
+        }
+    }
+}
+
+// One workgroup per request: reduce its partial sums and advance its state.
+template <int MODE>
+__global__ void __launch_bounds__(kFinThreads)
+ks_fin(const SrvHdr *hdr, const SrvDesc *d, int j, CgParams prm) {
+    __shared__ double s_scr[kFinThreads];
+    __shared__ double s_tot[3 * kSrvMaxK];
+    for (int r = blockIdx.x; r < hdr->n; r += gridDim.x) {
+        const SrvDesc &q = d[r];
+        if (MODE == FIN_INIT ? !q.init : j >= q.iters) continue;
+        const int nt = MODE == FIN_ALPHA ? q.tiles_s : q.tiles_v;
+        fin_sum(q.part, nt, fin_width(MODE, q.k), s_scr, s_tot);
+        if ((int)threadIdx.x < q.k) cg_state_update(MODE, q.st[threadIdx.x], s_tot, threadIdx.x, q.k, prm);
+        __syncthreads();
+    }
+}
+
+// r -= alpha q; partial sums of r.z (z = D^-1 r) and r.r.
+__global__ void __launch_bounds__(T)
+ks_update(const SrvHdr *hdr, const SrvDesc *d, int j) {
+    __shared__ double s_part[2 * kSrvMaxK];
+    __shared__ double s_red[T];
+    const int n = hdr->n, tot = hdr->tot_v;
+    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
+        const SrvDesc &q = d[find_req(d, n, v, SP_V)];
+        if (j >= q.iters) continue;
+        const int32_t tile = v - q.off_v;
+        const VLane L = vlane(q.k, q.KP);
+        const int64_t i = (int64_t)tile * L.gpb + L.grp;
+        const bool on = L.act && i < q.view.nV && q.st[L.c].active;
+        double dd[2] = {0.0, 0.0};
+        if (on) {
+            const R a = (R)q.st[L.c].alpha;
+            const int64_t e = i * q.k + L.c;
+            const R rv = q.r[e] - a * q.q[e];
+            const R zv = q.invD[i] * rv;
+            q.r[e] = rv;
+            dd[0] = (double)rv * (double)zv;
+            dd[1] = (double)rv * (double)rv;
+        }
+        column_partials(dd, 2, q.k, q.KP, on, s_red, s_part);
+        const int W = 2 * q.k;
+        if ((int)threadIdx.x < W) q.part[(size_t)threadIdx.x * q.tiles_v + tile] = s_part[threadIdx.x];
+        __syncthreads();
+    }
+}
+
+// x += alpha p; p = D^-1 r + beta p for columns still active.
+__global__ void __launch_bounds__(T)
+ks_pupdate(const SrvHdr *hdr, const SrvDesc *d, int j) {
+    const int n = hdr->n, tot = hdr->tot_v;
+    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
+        const SrvDesc &q = d[find_req(d, n, v, SP_V)];
+        if (j >= q.iters) continue;
+        const int32_t tile = v - q.off_v;
+        const VLane L = vlane(q.k, q.KP);
+        const int64_t i = (int64_t)tile * L.gpb + L.grp;
+        if (!L.act || i >= q.view.nV) continue;
+        const CgCol &s = q.st[L.c];
+        if (s.alpha == 0.0 && !s.active) continue;
+        const int64_t e = i * q.k + L.c;
+        const R pv = q.p[e];
+        q.u[e] += (R)s.alpha * pv;
+        if (s.active) q.p[e] = q.invD[i] * q.r[e] + (R)s.beta * pv;
+    }
+}
+
+// ------------------------------------------------------------- footprint
+
+int64_t rnd(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+int64_t tiles_for(int32_t nV, int rows) { return ((int64_t)nV + rows - 1) / rows; }
+
+// Upper bound of the bytes one request takes from the arena: its inputs, the
+// topology (persistent arrays and the temporaries of its construction, with
+// the edge count bounded by 3 nF) and its solver arrays.
+int64_t footprint_of(int32_t nV, int64_t nF, int32_t k, bool per_mesh_path) {
+    const int64_t nE = 3 * nF, nnz = (int64_t)nV + 2 * nE, V1 = (int64_t)nV + 1;
+    const int KP = pow2ceil(k), G = KP < 8 ? 8 : KP;
+    const int64_t tv = tiles_for(nV, T / KP), ts = tiles_for(nV, T / G);
+    int64_t b = 0;
+    b += rnd(12 * nF) + rnd(12 * (int64_t)nV) + rnd(4 * (int64_t)nV * k);  // F, X, f
+    // topology construction
+    b += rnd(12 * nF) + rnd(32) + 5 * rnd(4 * V1) + rnd(4 * (V1 / 1000 + 64)) + rnd(8 * 3 * nF);
+    b += rnd(8 * nE) + rnd(12 * nF) + rnd(3 * nF) + rnd(4 * V1) + rnd(4 * nnz) + rnd(4 * (int64_t)nV) +
+         rnd(4 * V1) + rnd(12 * nF) + rnd(nV) + rnd(12 * nF) + rnd(4 * nE);
+    // solver arrays
+    b += rnd(4 * nnz) + rnd(4 * (int64_t)nV) + 4 * rnd(4 * (int64_t)nV * k) + rnd(4 * (int64_t)nV);
+    b += rnd(8 * std::max<int64_t>(3 * k * tv, k * ts)) + rnd((int64_t)sizeof(CgCol) * k);
+    if (per_mesh_path) {
+        // the per-mesh PCG workspace (grown once, with headroom) and the
+        // assembly counter
+        const int64_t ws = 4 * rnd(4 * (int64_t)nV * k) + rnd(4 * (int64_t)nV) +
+                           rnd(8 * 1024 * 3 * 64) + rnd(80 * 64) + rnd(8 * 64) + 4096;
+        b += rnd(ws + ws / 4) + rnd(320);
+    }
+    return b + 8192;
+}
+
+// --------------------------------------------------------------- executor
+
+struct Bump {
+    char *base = nullptr;
+    int64_t cap = 0, used = 0;
+};
+
+void *bump_alloc(size_t bytes, dgo_stream, void *ctx) {
+    Bump *b = (Bump *)ctx;
+    const int64_t need = rnd((int64_t)bytes);
+    if (b->used + need > b->cap) return nullptr;
+    void *p = b->base + b->used;
+    b->used += need;
+    return p;
+}
+
+void bump_free(void *, dgo_stream, void *) {}  // the request's range is released whole
+
+struct ReqDev {
+    Bump bump;
+    dgo_mesh *mesh = nullptr;
+    SrvDesc desc{};
+};
+
+class GpuExec {
+  public:
+    explicit GpuExec(const dgo_server_opts &o) : o_(o) {}
+
+    dgo_status init() {
+        DGO_HIP(hipGetDevice(&dev_));
+        DGO_HIP(hipMalloc(&arena_, (size_t)o_.hbm_budget_bytes));
+        DGO_HIP(hipStreamCreateWithFlags(&cs_, hipStreamNonBlocking));
+        const size_t db = sizeof(SrvHdr) + sizeof(SrvDesc) * kSrvMaxSlots;
+        DGO_HIP(hipHostMalloc(&h_desc_, db, hipHostMallocDefault));
+        DGO_HIP(hipMalloc(&d_desc_, db));
+        DGO_HIP(hipMalloc(&d_ndeg_, 256));
+        DGO_HIP(hipMemset(d_ndeg_, 0, 256));
+        return DGO_OK;
+    }
+
+    ~GpuExec() {
+        if (graph_) (void)hipGraphExecDestroy(graph_);
+        for (auto &kv : prep_streams_) (void)hipStreamDestroy(kv.second);
+        if (cs_) (void)hipStreamDestroy(cs_);
+        if (h_desc_) (void)hipHostFree(h_desc_);
+        if (d_desc_) (void)hipFree(d_desc_);
+        if (d_ndeg_) (void)hipFree(d_ndeg_);
+        if (arena_) (void)hipFree(arena_);
+    }
+
+    int64_t footprint(const dgo_request &r) const {
+        return footprint_of(r.nV, r.nF, r.k, o_.batched == 0);
+    }
+
+    dgo_status prepare(srv::Req &q) {
+        (void)hipSetDevice(dev_);
+        hipStream_t ps = prep_stream();
+        ReqDev *rd = new (std::nothrow) ReqDev();
+        if (!rd) return DGO_ERR_NOMEM;
+        q.exec = rd;
+        rd->bump.base = (char *)arena_ + q.arena_off;
+        rd->bump.cap = q.footprint;
+        const dgo_request &in = q.in;
+        const int64_t nV = in.nV, k = in.k;
+        auto take = [&](int64_t bytes) { return bump_alloc((size_t)bytes, nullptr, &rd->bump); };
+        int32_t *dF = (int32_t *)take(12 * in.nF);
+        R *dX = (R *)take(12 * nV);
+        R *df = (R *)take(4 * nV * k);
+        if (!dF || !dX || !df) return DGO_ERR_NOMEM;
+        DGO_HIP(hipMemcpyAsync(dF, in.h_F, 12 * in.nF, hipMemcpyHostToDevice, ps));
+        DGO_HIP(hipMemcpyAsync(dX, in.h_X, 12 * nV, hipMemcpyHostToDevice, ps));
+        DGO_HIP(hipMemcpyAsync(df, in.h_f, 4 * nV * k, hipMemcpyHostToDevice, ps));
+        dgo_allocator al{bump_alloc, bump_free, &rd->bump};
+        dgo_status st = dgo_mesh_create(2, in.nV, in.nF, dF, &al, (dgo_stream)ps, &rd->mesh);
+        if (st != DGO_OK) return st;
+        dgo_mesh *m = rd->mesh;
+        SrvDesc &D = rd->desc;
+        D.view = view_of(m);
+        D.diag = m->diag;
+        D.nnz = m->nnz;
+        D.X = dX;
+        D.f = df;
+        D.k = in.k;
+        D.KP = pow2ceil(in.k);
+        const int G = D.KP < 8 ? 8 : D.KP;
+        D.tiles_v = (int32_t)tiles_for(in.nV, T / D.KP);
+        D.tiles_s = (int32_t)tiles_for(in.nV, T / G);
+        D.nblocks = m->nblocks;
+        D.K = (R *)take(4 * m->nnz);
+        D.M = (R *)take(4 * nV);
+        D.u = (R *)take(4 * nV * k);
+        D.r = (R *)take(4 * nV * k);
+        D.p = (R *)take(4 * nV * k);
+        D.q = (R *)take(4 * nV * k);
+        D.invD = (R *)take(4 * nV);
+        D.part = (double *)take(8 * std::max<int64_t>(3 * k * D.tiles_v, k * D.tiles_s));
+        D.st = (CgCol *)take((int64_t)sizeof(CgCol) * k);
+        if (!D.K || !D.M || !D.u || !D.r || !D.p || !D.q || !D.invD || !D.part || !D.st)
+            return DGO_ERR_NOMEM;
+        DGO_HIP(hipStreamSynchronize(ps));
+        return DGO_OK;
+    }
+
+    dgo_status tick(std::vector<srv::Req *> &active, int32_t chunk) {
+        (void)hipSetDevice(dev_);
+        if (o_.batched == 0) return tick_single(active);
+        const int n = (int)active.size();
+        SrvHdr *h = (SrvHdr *)h_desc_;
+        SrvDesc *hd = (SrvDesc *)((char *)h_desc_ + sizeof(SrvHdr));
+        int32_t oa = 0, os = 0, ov = 0;
+        for (int i = 0; i < n; ++i) {
+            srv::Req *q = active[i];
+            ReqDev *rd = (ReqDev *)q->exec;
+            SrvDesc D = rd->desc;
+            D.init = q->initialised ? 0 : 1;
+            D.iters = std::min(chunk, q->target - q->done_iters);
+            D.off_a = oa;
+            D.off_s = os;
+            D.off_v = ov;
+            oa += D.init ? D.nblocks : 0;
+            os += D.tiles_s;
+            ov += D.tiles_v;
+            hd[i] = D;
+        }
+        *h = SrvHdr{n, oa, os, ov};
+        const size_t bytes = sizeof(SrvHdr) + sizeof(SrvDesc) * n;
+        DGO_HIP(hipMemcpyAsync(d_desc_, h_desc_, bytes, hipMemcpyHostToDevice, cs_));
+        const bool use_graph = !trace_active() && !(getenv("DGO_SERVE_GRAPH") && atoi(getenv("DGO_SERVE_GRAPH")) == 0);
+        if (use_graph) {
+            if (!graph_ || graph_chunk_ != chunk) {
+                if (graph_) (void)hipGraphExecDestroy(graph_);
+                graph_ = nullptr;
+                hipGraph_t g = nullptr;
+                DGO_HIP(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
+                launch_tick(chunk);
+                DGO_HIP(hipStreamEndCapture(cs_, &g));
+                hipError_t e = hipGraphInstantiate(&graph_, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    graph_ = nullptr;
+                    return hip_fail(e, "hipGraphInstantiate", __FILE__, __LINE__);
+                }
+                graph_chunk_ = chunk;
+            }
+            DGO_HIP(hipGraphLaunch(graph_, cs_));
+        } else {
+            launch_tick(chunk);
+        }
+        DGO_HIP(hipGetLastError());
+        DGO_HIP(hipStreamSynchronize(cs_));
+        for (int i = 0; i < n; ++i) active[i]->done_iters += hd[i].iters;
+        return DGO_OK;
+    }
+
+    dgo_status finish(srv::Req &q) {
+        ReqDev *rd = (ReqDev *)q.exec;
+        (void)hipSetDevice(dev_);
+        DGO_HIP(hipMemcpyAsync(q.in.h_u, rd->desc.u, 4 * (size_t)q.in.nV * q.in.k,
+                               hipMemcpyDeviceToHost, cs_));
+        DGO_HIP(hipStreamSynchronize(cs_));
+        return DGO_OK;
+    }
+
+    void release(srv::Req &q) {
+        ReqDev *rd = (ReqDev *)q.exec;
+        if (!rd) return;
+        (void)hipSetDevice(dev_);
+        if (rd->mesh) dgo_mesh_destroy(rd->mesh);
+        delete rd;
+        q.exec = nullptr;
+    }
+
+  private:
+    hipStream_t prep_stream() {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto id = std::this_thread::get_id();
+        auto it = prep_streams_.find(id);
+        if (it != prep_streams_.end()) return it->second;
+        hipStream_t s = nullptr;
+        (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        prep_streams_[id] = s;
+        return s;
+    }
+
+    void launch_tick(int32_t chunk) {
+        const SrvHdr *hd = (const SrvHdr *)d_desc_;
+        const SrvDesc *dd = (const SrvDesc *)((char *)d_desc_ + sizeof(SrvHdr));
+        const R a = (R)o_.alpha, b = (R)o_.beta;
+        CgParams prm;
+        prm.rtol = 0.0;
+        prm.max_iter = o_.cg_iters;
+        prm.fixed = 1;
+        prm.stall = 0;
+        prm.k = 0;
+        const unsigned nfin = (unsigned)std::min(o_.max_slots, kSrvMaxSlots);
+        DGO_LAUNCH("srv_assemble", cs_,
+                   ks_assemble<<<kSrvAsmBlocks, kAssembleThreads, kRowBlockLdsBytes, cs_>>>(hd, dd, d_ndeg_));
+        DGO_LAUNCH("srv_init", cs_, ks_init<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, a, b));
+        DGO_LAUNCH("srv_fin", cs_, ks_fin<FIN_INIT><<<nfin, kFinThreads, 0, cs_>>>(hd, dd, 0, prm));
+        for (int j = 0; j < chunk; ++j) {
+            DGO_LAUNCH("srv_spmm", cs_, ks_spmm<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, j, a, b));
+            DGO_LAUNCH("srv_fin", cs_, ks_fin<FIN_ALPHA><<<nfin, kFinThreads, 0, cs_>>>(hd, dd, j, prm));
+            DGO_LAUNCH("srv_update", cs_, ks_update<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, j));
+            DGO_LAUNCH("srv_fin", cs_, ks_fin<FIN_BETA><<<nfin, kFinThreads, 0, cs_>>>(hd, dd, j, prm));
+            DGO_LAUNCH("srv_pupdate", cs_, ks_pupdate<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, j));
+        }
+    }
+
+    // One request with the per-mesh entry points (the baseline path).
+    dgo_status tick_single(std::vector<srv::Req *> &active) {
+        for (srv::Req *q : active) {
+            ReqDev *rd = (ReqDev *)q->exec;
+            const SrvDesc &D = rd->desc;
+            dgo_stream s = (dgo_stream)cs_;
+            DGO_TRY(dgo_assemble(rd->mesh, DGO_F32, 1, D.X, nullptr, D.K, D.M, nullptr, s));
+            DGO_TRY(dgo_spmv(rd->mesh, DGO_F32, 1, 1.0, D.M, 0.0, D.K, D.k, D.f, D.r, s));
+            DGO_HIP(hipMemsetAsync(D.u, 0, 4 * (size_t)D.view.nV * D.k, cs_));
+            dgo_cg_opts co{};
+            co.rtol = 0.0;
+            co.max_iter = q->target;
+            co.fixed_iters = 1;
+            co.check_every = q->target;
+            DGO_TRY(dgo_pcg(rd->mesh, DGO_F32, o_.alpha, D.M, o_.beta, D.K, nullptr, nullptr, D.k,
+                            D.r, D.u, &co, nullptr, s));
+            q->done_iters = q->target;
+        }
+        return DGO_OK;
+    }
+
+    dgo_server_opts o_;
+    int dev_ = 0;
+    void *arena_ = nullptr, *h_desc_ = nullptr, *d_desc_ = nullptr;
+    int32_t *d_ndeg_ = nullptr;
+    hipStream_t cs_ = nullptr;
+    hipGraphExec_t graph_ = nullptr;
+    int32_t graph_chunk_ = -1;
+    std::mutex mu_;
+    std::unordered_map<std::thread::id, hipStream_t> prep_streams_;
+};
+
+}  // namespace
+}  // namespace dgo
+
+using namespace dgo;
+
+struct dgo_server {
+    GpuExec *ex = nullptr;
+    srv::Scheduler<GpuExec> *sch = nullptr;
+};
+
+extern "C" int64_t dgo_server_footprint(int32_t nV, int64_t nF, int32_t k) {
+    if (nV < 1 || nF < 1 || k < 1) return -1;
+    return footprint_of(nV, nF, k, false);
+}
+
+extern "C" dgo_status dgo_server_create(const dgo_server_opts *opts, dgo_server **out) {
+    clear_error();
+    if (!opts || !out) return fail(DGO_ERR_INVALID_ARG, "dgo_server_create: NULL argument");
+    *out = nullptr;
+    dgo_server_opts o = *opts;
+    if (o.max_slots < 1 || o.max_slots > kSrvMaxSlots || o.cg_iters < 1 || o.cg_chunk < 0 ||
+        o.hbm_budget_bytes <= 0 || o.prep_threads < 0)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_server_create: bad options");
+    if (o.cg_chunk == 0 || o.cg_chunk > o.cg_iters) o.cg_chunk = o.cg_iters;
+    if (o.prep_threads == 0) o.prep_threads = 2;
+    if (!o.batched) {
+        o.max_slots = 1;
+        o.cg_chunk = o.cg_iters;
+    }
+    dgo_server *s = new (std::nothrow) dgo_server();
+    if (!s) return fail(DGO_ERR_NOMEM, "dgo_server_create: host allocation failed");
+    s->ex = new (std::nothrow) GpuExec(o);
+    if (!s->ex) {
+        delete s;
+        return fail(DGO_ERR_NOMEM, "dgo_server_create: host allocation failed");
+    }
+    const dgo_status st = s->ex->init();
+    if (st != DGO_OK) {
+        delete s->ex;
+        delete s;
+        return st;
+    }
+    s->sch = new srv::Scheduler<GpuExec>(*s->ex, o);
+    *out = s;
+    return DGO_OK;
+}
+
+extern "C" dgo_status dgo_server_submit(dgo_server *s, const dgo_request *r, uint64_t *ticket) {
+    clear_error();
+    if (!s || !r || !ticket) return fail(DGO_ERR_INVALID_ARG, "dgo_server_submit: NULL argument");
+    if (r->nV < 3 || r->nF < 1 || r->k < 1 || r->k > kSrvMaxK || !r->h_F || !r->h_X || !r->h_f ||
+        !r->h_u)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_server_submit: bad request (nV >= 3, nF >= 1, 1 <= k <= 16, buffers)");
+    const dgo_status st = s->sch->submit(*r, ticket);
+    if (st == DGO_ERR_BUDGET) return fail(st, "dgo_server_submit: request larger than the HBM budget");
+    if (st == DGO_ERR_SHUTDOWN) return fail(st, "dgo_server_submit: server is shutting down");
+    return st;
+}
+
+extern "C" dgo_status dgo_server_wait(dgo_server *s, uint64_t ticket, double timeout_s,
+                                      dgo_req_stats *st) {
+    clear_error();
+    if (!s) return fail(DGO_ERR_INVALID_ARG, "dgo_server_wait: NULL server");
+    const dgo_status r = s->sch->wait(ticket, timeout_s, st);
+    if (r == DGO_ERR_TIMEOUT) return fail(r, "dgo_server_wait: timed out");
+    if (r == DGO_ERR_INVALID_ARG) return fail(r, "dgo_server_wait: unknown ticket");
+    if (r != DGO_OK) return fail(r, "dgo_server_wait: the request failed");
+    return r;
+}
+
+extern "C" dgo_status dgo_server_stats(dgo_server *s, dgo_server_counters *out) {
+    clear_error();
+    if (!s || !out) return fail(DGO_ERR_INVALID_ARG, "dgo_server_stats: NULL argument");
+    s->sch->stats(out);
+    return DGO_OK;
+}
+
+extern "C" void dgo_server_destroy(dgo_server *s) {
+    if (!s) return;
+    delete s->sch;  // drains
+    delete s->ex;
+    delete s;
+}

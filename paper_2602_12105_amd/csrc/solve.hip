@@ -27,6 +27,7 @@
 // result is bitwise deterministic run to run. Columns stop independently and
 // are frozen once stopped.
 #include "internal.hpp"
+#include "kernels.hpp"
 
 #include <algorithm>
 #include <cstdlib>
@@ -35,171 +36,7 @@
 namespace dgo {
 namespace {
 
-constexpr int T = 256;
-constexpr int kMaxK = 64;
-constexpr int kMaxBlocks = 4096; // workgroups of a streaming kernel
-constexpr int kMaxRedBlocks = 1024; // workgroups of a kernel that stores partial sums
-constexpr int kFinThreads = 1024;
-constexpr int kVecUnroll = 1;     // rows per thread per step in the vector kernels (measured best)
-
-struct CgCol {
-    double rz, pq, alpha, beta, rr, bb, best;
-    int32_t iters, since, active, converged;
-    int32_t stalled, pad0;
-};
-
-struct CgParams {
-    double rtol;
-    int32_t max_iter, fixed, stall;
-    int32_t k;
-};
-
-
-int pow2ceil(int k) {
-    int G = 1;
-    while (G < k) G *= 2;
-    return G;
-}
-
-// Contiguous chunk of tiles for this workgroup; each XCD's workgroups cover
-// one contiguous range of tiles, so neighbouring rows share an L2.
-__device__ __forceinline__ void tile_range(int64_t ntiles, int64_t &t0, int64_t &t1) {
-    const uint32_t nb = gridDim.x;
-    const uint32_t lb = xcd_tile(blockIdx.x, nb);
-    const int64_t per = (ntiles + nb - 1) / nb;
-    t0 = (int64_t)lb * per;
-    t1 = t0 + per < ntiles ? t0 + per : ntiles;
-}
-
-// ------------------------------------------------------ fixed-order reduce
-
-// Store the workgroup's W partial sums (LDS) column-major, at
-// part[w * gridDim.x + blockIdx.x], so that the finalize kernel reads each
-// value's partials as one contiguous run.
-__device__ __forceinline__ void store_partials(const double *s_part, int W, double *part) {
-    if ((int)threadIdx.x < W) part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s_part[threadIdx.x];
-}
-
-// tot[w] = sum over b < nblk of part[w * nblk + b] in a fixed order, computed by
-// one workgroup of kFinThreads threads: thread t sums the strided subset
-// b = t % tpw (mod tpw) of value w = t / tpw (loads issued kFinUnroll at a
-// time, added in order), then thread w adds its tpw subtotals in order.
-constexpr int kFinUnroll = 16;
-
-__device__ void fin_sum(const double *__restrict__ part, int nblk, int W, double *scr,
-                        double *tot) {
-    const int t = threadIdx.x;
-    const int tpw = kFinThreads / W;
-    const int w = t / tpw, sub = t % tpw;
-    double s = 0.0;
-    if (w < W) {
-        for (int b0 = sub; b0 < nblk; b0 += tpw * kFinUnroll) {
-            double v[kFinUnroll];
-#pragma unroll
-            for (int u = 0; u < kFinUnroll; ++u) {
-                const int b = b0 + u * tpw;
-                v[u] = b < nblk ? part[(size_t)w * nblk + b] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < kFinUnroll; ++u) s += v[u];
-        }
-    }
-    scr[t] = s;
-    __syncthreads();
-    if (t < W) {
-        double a = 0.0;
-        for (int j = 0; j < tpw; ++j) a += scr[t * tpw + j];
-        tot[t] = a;
-    }
-    __syncthreads();
-}
-
-// Per-column workgroup partials of per-lane values: column c lives in lanes
-// whose index within their group of G lanes is c.
-__device__ __forceinline__ void column_partials(const double *vals, int nval, int k, int G,
-                                                bool act, double *s_red, double *s_part) {
-    for (int v = 0; v < nval; ++v) {
-        __syncthreads();
-        s_red[threadIdx.x] = act ? vals[v] : 0.0;
-        __syncthreads();
-        if ((int)threadIdx.x < k) {
-            double a = 0.0;
-            for (int t = threadIdx.x; t < T; t += G) a += s_red[t];
-            s_part[v * k + threadIdx.x] = a;
-        }
-    }
-    __syncthreads();
-}
-
-// ------------------------------------------------------------------ SpMM
-
-// RU rows of (alpha M + beta K) x for the calling group of G lanes, all
-// loads of the RU rows issued together. ok[u] = false rows yield 0. The
-// results are meaningful in lanes lane < KP with lane < k.
-template <typename R, int G, int KP, bool MASK, int RU>
-__device__ __forceinline__ void rows_core(const int32_t *__restrict__ rowptr,
-                                          const int32_t *__restrict__ col,
-                                          const R *__restrict__ K, const R *__restrict__ M,
-                                          R alpha, R beta, const uint8_t *__restrict__ mask,
-                                          const R *__restrict__ x, const int32_t (&i)[RU],
-                                          const bool (&ok)[RU], int k, int lane, int gbase,
-                                          R (&acc)[RU]) {
-    constexpr int NP = G / KP;
-    const int c = lane % KP, part = lane / KP;
-    const int cc = c < k ? c : k - 1;
-    int32_t rb[RU], re[RU];
-    R dterm[RU];
-    int32_t len = 0;
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-        rb[u] = ok[u] ? rowptr[i[u]] : 0;
-        re[u] = ok[u] ? rowptr[i[u] + 1] : 0;
-        dterm[u] = ok[u] ? alpha * M[i[u]] : R(0);
-        len = max(len, re[u] - rb[u]);
-        acc[u] = 0;
-    }
-    for (int32_t e0 = 0; e0 < len; e0 += G) {
-        int32_t cj[RU];
-        R aj[RU];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int32_t e = rb[u] + e0 + lane;
-            cj[u] = 0;
-            aj[u] = 0;
-            if (e < re[u]) {
-                const int32_t j = col[e];
-                if (!MASK || !mask[j]) {
-                    cj[u] = j;
-                    aj[u] = beta * K[e];
-                    if (j == i[u]) aj[u] += dterm[u];
-                }
-            }
-        }
-        if (KP == 1) {
-#pragma unroll
-            for (int u = 0; u < RU; ++u) acc[u] += aj[u] * x[cj[u]];
-        } else {
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-#pragma unroll
-                for (int s = 0; s < KP; ++s) {
-                    const int t = s * NP + part;
-                    const int32_t j = __shfl(cj[u], gbase + t);
-                    const R a = __shfl(aj[u], gbase + t);
-                    acc[u] += a * x[(int64_t)j * k + cc];
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-#pragma unroll
-        for (int off = G / 2; off >= KP; off /= 2) acc[u] += __shfl_down(acc[u], off, G);
-    }
-}
-
-// Rows handled together by one lane group.
-constexpr int kRowsInFlight = 1;
+using namespace kern;
 
 template <typename R, int KP>
 __global__ void __launch_bounds__(T)
@@ -289,22 +126,6 @@ k_cg_spmm_dot(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ co
     if (!part) return;
     column_partials(&dsum, 1, k, G, out_lane, s_red, s_part);
     store_partials(s_part, k, part);
-}
-
-// Lane layout of the vector kernels: KP lanes per row, lane c owns column c.
-struct VLane {
-    int c;
-    bool act;
-    int grp, gpb;
-};
-
-__device__ __forceinline__ VLane vlane(int k, int KP) {
-    VLane v;
-    v.c = threadIdx.x % KP;
-    v.act = v.c < k;
-    v.grp = threadIdx.x / KP;
-    v.gpb = T / KP;
-    return v;
 }
 
 // r = beff - q, p = D^-1 r; partial sums of r.z, r.r, beff.beff.
@@ -415,8 +236,6 @@ k_cg_pupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ p,
     }
 }
 
-enum FinMode { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUT = 3 };
-
 // One workgroup: add the partial sums of the preceding kernel in a fixed
 // order, then update the per-column state (or store the totals).
 template <int MODE>
@@ -425,55 +244,14 @@ k_cg_fin(const double *__restrict__ part, int nblk, int k, CgCol *st, CgParams p
          double *out) {
     __shared__ double s_scr[kFinThreads];
     __shared__ double s_tot[3 * kMaxK];
-    const int W = (MODE == FIN_INIT ? 3 : (MODE == FIN_BETA ? 2 : 1)) * k;
-    fin_sum(part, nblk, W, s_scr, s_tot);
+    fin_sum(part, nblk, fin_width(MODE, k), s_scr, s_tot);
     const int c = threadIdx.x;
     if (c >= k) return;
     if (MODE == FIN_OUT) {
         out[c] = s_tot[c];
         return;
     }
-    CgCol &s = st[c];
-    if (MODE == FIN_INIT) {
-        s.rz = s_tot[c];
-        s.rr = s_tot[k + c];
-        s.bb = s_tot[2 * k + c];
-        s.best = s.rr;
-        s.iters = 0;
-        s.since = 0;
-        s.stalled = 0;
-        s.pq = 0.0;
-        s.alpha = 0.0;
-        s.beta = 0.0;
-        const bool conv = !prm.fixed && sqrt(s.rr) <= prm.rtol * sqrt(s.bb);
-        s.converged = conv ? 1 : 0;
-        s.active = (!conv && prm.max_iter > 0) ? 1 : 0;
-    } else if (MODE == FIN_ALPHA) {
-        const double pq = s_tot[c];
-        s.pq = pq;
-        s.alpha = (s.active && pq != 0.0) ? s.rz / pq : 0.0;
-    } else if (s.active) {  // FIN_BETA
-        const double rz_new = s_tot[c], rr = s_tot[k + c];
-        s.beta = s.rz != 0.0 ? rz_new / s.rz : 0.0;
-        s.rz = rz_new;
-        s.rr = rr;
-        s.iters += 1;
-        if (rr < s.best) {
-            s.best = rr;
-            s.since = 0;
-        } else {
-            s.since += 1;
-        }
-        if (!prm.fixed && sqrt(rr) <= prm.rtol * sqrt(s.bb)) {
-            s.converged = 1;
-            s.active = 0;
-        } else if (s.iters >= prm.max_iter) {
-            s.active = 0;
-        } else if (!prm.fixed && prm.stall > 0 && s.since >= prm.stall) {
-            s.stalled = 1;
-            s.active = 0;
-        }
-    }
+    cg_state_update(MODE, st[c], s_tot, c, k, prm);
 }
 
 // 1 / (alpha M_ii + beta K_ii); zero on masked rows.

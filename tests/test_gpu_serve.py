@@ -1,0 +1,116 @@
+"""GPU tests of the serving loop: batched results against the FP64 oracle
+(same iteration count on FP32-rounded inputs), bitwise equality of a request
+alone and in a mix, continuous batching of late arrivals, budget rejection and
+per-request failure isolation."""
+import numpy as np
+import pytest
+import torch
+
+import meshgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+dgo = pytest.importorskip("paper_2602_12105_amd")
+from paper_2602_12105_amd.serve import Server, footprint  # noqa: E402
+
+ITERS = 50
+
+
+def _request(kind, size, k, seed):
+    if kind == "grid":
+        X, F = meshgen.grid2d(size, 0.2, seed)
+    else:
+        X, F = meshgen.icosphere(size, 1e-3, seed)
+    f = meshgen.normal(seed + 7, X.shape[0] * k).reshape(-1, k)
+    return F, X.astype(np.float32), f.astype(np.float32)
+
+
+def _oracle(F, X, f, iters=ITERS):
+    X64 = X.astype(np.float64)
+    K, M, rp, col = oracle.assemble(X64, F)
+    b = M[:, None] * f.astype(np.float64)
+    u, its, _ = oracle.pcg(rp, col, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=iters)
+    return u
+
+
+MIX = [("grid", 12, 1), ("ico", 3, 8), ("grid", 31, 16), ("ico", 2, 3), ("grid", 7, 5),
+       ("ico", 4, 12), ("grid", 20, 2), ("ico", 1, 16)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible")
+    yield
+
+
+def test_batched_matches_oracle_and_is_mix_independent():
+    print("[serve] mix vs oracle", flush=True)
+    reqs = [_request(kd, sz, k, 100 + i) for i, (kd, sz, k) in enumerate(MIX)]
+    with Server(hbm_budget_bytes=1 << 30, max_slots=16, cg_iters=ITERS, cg_chunk=10) as s:
+        tickets = [s.submit(F, X, f, user=i) for i, (F, X, f) in enumerate(reqs)]
+        outs = [s.wait(t)[0].copy() for t in tickets]
+        st = s.stats()
+    assert st["completed"] == len(MIX) and st["failed"] == 0 and st["hbm_in_use"] == 0
+    for (F, X, f), u in zip(reqs, outs):
+        ref = _oracle(F, X, f)
+        err = np.abs(u.astype(np.float64) - ref).max() / np.abs(ref).max()
+        assert err <= 1e-4, err
+    # alone: the same request on an otherwise empty server gives the same bits
+    for i in (2, 5):
+        F, X, f = reqs[i]
+        with Server(hbm_budget_bytes=1 << 30, max_slots=16, cg_iters=ITERS, cg_chunk=10) as s:
+            alone = s.wait(s.submit(F, X, f))[0]
+        np.testing.assert_array_equal(alone, outs[i])
+
+
+def test_baseline_agrees_with_batched():
+    print("[serve] baseline", flush=True)
+    reqs = [_request(kd, sz, k, 200 + i) for i, (kd, sz, k) in enumerate(MIX[:4])]
+    outs = {}
+    for batched in (True, False):
+        with Server(hbm_budget_bytes=1 << 30, max_slots=8, cg_iters=ITERS, cg_chunk=10,
+                    batched=batched) as s:
+            ts = [s.submit(F, X, f) for F, X, f in reqs]
+            outs[batched] = [s.wait(t)[0].copy() for t in ts]
+    for a, b in zip(outs[True], outs[False]):
+        assert np.abs(a - b).max() <= 1e-4 * np.abs(b).max()
+
+
+def test_continuous_batching_and_admission():
+    print("[serve] continuous batching", flush=True)
+    big = _request("ico", 6, 16, 1)
+    small = [_request("grid", 9 + i, 4, 300 + i) for i in range(6)]
+    with Server(hbm_budget_bytes=1 << 30, max_slots=8, cg_iters=ITERS, cg_chunk=5) as s:
+        t0 = s.submit(*big)
+        ts = [s.submit(*r) for r in small]
+        u0, st0 = s.wait(t0)
+        sts = [s.wait(t)[1] for t in ts]
+        c = s.stats()
+    assert c["max_batch"] > 1
+    # small requests were admitted while the large one was still running
+    assert any(st["t_start"] < st0["t_done"] for st in sts)
+    assert all(st["iters"] == ITERS for st in sts) and st0["iters"] == ITERS
+
+
+def test_budget_and_failure_isolation():
+    print("[serve] budget and failures", flush=True)
+    F, X, f = _request("grid", 40, 4, 5)
+    fp = footprint(X.shape[0], F.shape[0], 4)
+    with Server(hbm_budget_bytes=fp // 2, max_slots=4, cg_iters=10, cg_chunk=10) as s:
+        with pytest.raises(dgo.DgoError) as e:
+            s.submit(F, X, f)
+        assert e.value.status == "BUDGET"
+    bad = F.copy()
+    bad[3, 1] = X.shape[0] + 5  # index out of range
+    with Server(hbm_budget_bytes=1 << 28, max_slots=4, cg_iters=10, cg_chunk=10) as s:
+        tb = s.submit(bad, X, f)
+        tg = s.submit(F, X, f)
+        with pytest.raises(dgo.DgoError) as e:
+            s.wait(tb)
+        assert e.value.status == "INDEX_RANGE"
+        u, st = s.wait(tg)
+        assert st["iters"] == 10 and np.isfinite(u).all()
+        c = s.stats()
+    assert c["failed"] == 1 and c["completed"] == 1 and c["hbm_in_use"] == 0
