@@ -19,6 +19,7 @@ time. `cpu_baseline` times the FP64 oracle (single thread) on the same step.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -28,6 +29,16 @@ import time
 HBM_PEAK_GBS = 8000.0
 
 PAPER_NOTE = "paper publishes no figure for this metric/workload"
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on this
+# workload, scaled by the same counters on a plain copy of known size
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_icosphere_L7_f64.json")
+# the sources whose change makes a stored traffic figure stale
+KERNEL_SOURCES = ["paper_2602_12105_amd/csrc/internal.hpp",
+                  "paper_2602_12105_amd/csrc/kernels.hpp",
+                  "paper_2602_12105_amd/csrc/assemble.hip",
+                  "paper_2602_12105_amd/csrc/solve.hip"]
 
 
 def parse():
@@ -43,6 +54,13 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--no-suite", action="store_true",
                     help="skip the other workloads (tets, grid, VJP batch, size sweep)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-pool", type=int, default=256,
+                    help="distinct generated payloads the arrivals are drawn from")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a plain elementwise copy of 256 MiB (read) into 256 MiB "
+                         "(write), the reference for scaling the HBM byte counters")
     return ap.parse_args()
 
 
@@ -71,6 +89,30 @@ def alg_bytes(kind, s, nV, nF, nnz, k):
         # read x p r, write x p, read D^-1
         return 5 * k * s * nV + s * nV
     return None
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, dtype, level):
+    """Counter-measured HBM bytes per launch of `kernel`, or None when no
+    measurement exists for this workload or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (d.get("sources_sha256") != kernel_sources_sha256() or d.get("dtype") != dtype
+            or d.get("level") != level):
+        return None
+    e = d.get("kernels", {}).get(kernel)
+    return None if e is None else e.get("bytes_per_launch")
 
 
 def main():
@@ -162,7 +204,8 @@ def main():
     dom = max((n for n in kernels if "gbps" in kernels[n]), key=lambda n: kernels[n]["ms_per_step"])
     dk = kernels[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["gbps"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": dk["frac"], "traffic": None,
+                "unit": "GB/s", "frac": dk["frac"],
+                "traffic": measured_traffic(dom, args.dtype, args.level),
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_us": dk["avg_us"]}
 
     # kernel-level rooflines outside the solve: assembly and SpMM (k = 8 and 1),
@@ -231,9 +274,17 @@ def main():
 
     if not args.no_suite:
         out["suite"] = suite(args, dgo, torch, meshgen)
+    if not args.no_serving:
+        out["serving"] = serving(args, meshgen)
     if not args.no_cpu_baseline:
         log(args, "cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(X, F, f, args.cpu_seconds)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        b_ = torch.empty_like(a)
+        for _ in range(3):
+            torch.add(a, 1.0, out=b_)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 
@@ -372,6 +423,112 @@ def suite(args, dgo, torch, meshgen):
     del flush
     torch.cuda.empty_cache()
     return out
+
+
+def _serve_payloads(meshgen, n_pool, seed=0):
+    """Synthetic requests: vertex count ~ logU[1e3, 2e5], grid or icosphere
+    (p = 1/2), k ~ U{1..16}, f ~ N(0, 1), FP32."""
+    import numpy as np
+    specs = meshgen.serving_requests(n_pool, seed)
+    base = {}
+    pool = []
+    for sp in specs:
+        key = (sp["kind"], sp["size"])
+        if key not in base:
+            base[key] = (meshgen.grid2d(sp["size"]) if sp["kind"] == "grid"
+                         else meshgen.icosphere(sp["size"]))
+        X0, F = base[key]
+        if sp["kind"] == "grid":
+            n = sp["size"]
+            X, _ = meshgen.grid2d(n, 0.2, sp["mesh_seed"])
+        else:
+            xi = meshgen.normal(sp["mesh_seed"], X0.shape[0])
+            X = X0 * (1.0 + 1e-3 * xi)[:, None]
+        f = meshgen.normal(sp["rhs_seed"], X.shape[0] * sp["k"]).reshape(-1, sp["k"])
+        pool.append((F, X.astype(np.float32), f.astype(np.float32), sp))
+    return pool
+
+
+def _run_server(dgo_serve, pool, n_req, rate, batched, seed):
+    """Submit n_req requests drawn cyclically from the pool, as a Poisson
+    stream of the given rate (req/s; None = all at once); returns
+    throughput and latency percentiles on the server's clock."""
+    import threading
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, n_req) if rate else np.zeros(n_req)
+    srv = dgo_serve.Server(hbm_budget_bytes=32 << 30, max_slots=128 if batched else 1,
+                           cg_iters=50, cg_chunk=10, batched=batched, prep_threads=3)
+    tickets = [None] * n_req
+    submitted = threading.Event()
+    lat, starts, ends = [], [], []
+
+    def producer():
+        t_next = time.perf_counter()
+        for r in range(n_req):
+            t_next += gaps[r]
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            F, X, f, _ = pool[r % len(pool)]
+            tickets[r] = srv.submit(F, X, f, user=r)
+            if r == 0:
+                submitted.set()
+
+    th = threading.Thread(target=producer)
+    t0 = time.perf_counter()
+    th.start()
+    submitted.wait()
+    for r in range(n_req):
+        while tickets[r] is None:
+            time.sleep(0.0005)
+        _, st = srv.wait(tickets[r], timeout=600.0)
+        lat.append(st["t_done"] - st["t_submit"])
+        starts.append(st["t_submit"])
+        ends.append(st["t_done"])
+    th.join()
+    wall = time.perf_counter() - t0
+    c = srv.stats()
+    srv.close()
+    lat = np.array(lat) * 1e3
+    span = max(ends) - min(starts)
+    return {"requests": n_req, "offered_rate": rate, "req_per_s": n_req / span,
+            "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "max_batch": c["max_batch"], "ticks": c["ticks"], "hbm_peak": c["hbm_peak"],
+            "gpu_busy_frac": c["busy_s"] / span}
+
+
+def serving(args, meshgen):
+    """Continuous batching vs one request at a time (each with its own
+    per-mesh launches): closed-loop capacity of the batched server, then a
+    Poisson stream at 0.8 x that capacity offered to both."""
+    import numpy as np
+    from paper_2602_12105_amd import serve as dgo_serve
+    log(args, f"serving: generating {args.serve_pool} payloads")
+    pool = _serve_payloads(meshgen, args.serve_pool)
+    nv = np.array([p[1].shape[0] for p in pool])
+    ks = np.array([p[2].shape[1] for p in pool])
+    n = args.serve_requests
+    log(args, "serving: closed loop (batched)")
+    cap = _run_server(dgo_serve, pool, n, None, True, 1)
+    rate = 0.8 * cap["req_per_s"]
+    log(args, f"serving: Poisson {rate:.0f} req/s (batched)")
+    b = _run_server(dgo_serve, pool, n, rate, True, 2)
+    log(args, "serving: closed loop (one request at a time)")
+    cap1 = _run_server(dgo_serve, pool, max(64, n // 8), None, False, 3)
+    log(args, f"serving: Poisson {rate:.0f} req/s (one request at a time)")
+    one = _run_server(dgo_serve, pool, max(64, n // 8), rate, False, 4)
+    return {"workload": f"{n} requests, nV ~ logU[1e3, 2e5] (mean {nv.mean():.0f}), "
+                        f"k ~ U{{1..16}} (mean {ks.mean():.1f}), FP32, assembly + 50 PCG "
+                        "iterations on (M + 1e-3 K) u = M f",
+            "payload_pool": len(pool),
+            "batched_closed_loop": cap, "batched_poisson": b,
+            "one_at_a_time_closed_loop": cap1, "one_at_a_time_poisson": one,
+            "speedup_req_per_s": b["req_per_s"] / one["req_per_s"],
+            "note": "one-at-a-time runs use n/8 requests of the same stream (its queue "
+                    "grows without bound at the offered rate)"}
 
 
 def cpu_baseline(X, F, f, budget_s):
