@@ -79,15 +79,16 @@ def alg_bytes(kind, s, nV, nF, nnz, k):
     if kind == "assemble_vjp_tri":
         # X, gK, gM read, gX written, triangles
         return 3 * s * nV + 12 * nF + s * nnz + s * nV + 3 * s * nV
-    if kind in ("spmm", "cg_spmm_dot"):
-        # CSR values + columns, row pointers, mass diagonal, x read, y written
+    if kind in ("spmm", "cg_spmm_dot", "cg_sdot"):
+        # CSR values + columns, row pointers, a diagonal (mass, or D^-1), x
+        # read, y written
         return nnz * (s + 4) + 4 * (nV + 1) + s * nV + 2 * k * s * nV
-    if kind == "cg_update":
-        # read r q, write r, read D^-1
-        return 3 * k * s * nV + s * nV
-    if kind == "cg_pupdate":
-        # read x p r, write x p, read D^-1
-        return 5 * k * s * nV + s * nV
+    if kind == "cg_vupdate":
+        # read r w p s x, write p s x r, read D^-1
+        return 9 * k * s * nV + s * nV
+    if kind == "cg_values":
+        # K, columns, row pointers, M, D^-1 read; scaled values written
+        return nnz * (2 * s + 4) + 4 * (nV + 1) + 2 * s * nV
     return None
 
 

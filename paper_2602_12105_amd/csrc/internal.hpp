@@ -98,6 +98,10 @@ struct dgo_mesh {
     int32_t *vtptr = nullptr;      // nV + 1, incidence offsets
     uint32_t *inc = nullptr;       // n_inc packed incidence records
     uint8_t *bmask = nullptr;      // nV boundary mask
+    // row order of the SpMV kernels: position r visits row rdesc[r].x, whose
+    // CSR entries start at rdesc[r].y, rlen[r] of them
+    int2 *rdesc = nullptr;         // nV
+    uint8_t *rlen = nullptr;       // nV
 
     // row blocks for the row-centric kernels
     int32_t rpb = 0;            // rows per workgroup
@@ -122,6 +126,25 @@ namespace dgo {
 
 // True while kernel tracing is enabled (graphs are not used then).
 bool trace_active();
+
+// Build a mesh (dgo_mesh_create). `rows` selects the row descriptors of the
+// SpMV kernels: none (a mesh swept only by the serving loop's batched
+// kernels, which never reach the SpMV entry points), natural order, or
+// automatic (breadth-first order for meshes of at least kRowOrderMinRows
+// vertices, natural below).
+enum RowsMode { ROWS_NONE = 0, ROWS_NATURAL = 1, ROWS_AUTO = 2 };
+constexpr int32_t kRowOrderMinRows = 16384;
+dgo_status mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_t *d_elem,
+                       const dgo_allocator *alloc, hipStream_t s, RowsMode rows,
+                       dgo_mesh **out);
+
+// Workspace of one PCG solve (byte offsets): vectors r, p, s, w, the
+// effective right-hand side, D^-1, the scaled operator values, two arrays of
+// workgroup partial sums, the per-column state and the true residuals.
+struct PcgLayout {
+    size_t off_r, off_p, off_s, off_w, off_b, off_d, off_v, off_pt, off_pt2, off_st, off_tr, total;
+};
+PcgLayout pcg_layout(int64_t nV, int64_t nnz, int k, size_t elem);
 
 // Release the cached graph of a mesh (if any).
 void mesh_drop_graph(dgo_mesh *m);

@@ -11,7 +11,8 @@ namespace kern {
 constexpr int T = 256;
 constexpr int kMaxK = 64;
 constexpr int kMaxBlocks = 4096; // workgroups of a streaming kernel
-constexpr int kMaxRedBlocks = 1024; // workgroups of a kernel that stores partial sums
+constexpr int kMaxRedBlocks = 512;  // workgroups of a kernel that stores partial sums
+constexpr int TR = 1024;            // threads per workgroup of such a kernel
 constexpr int kFinThreads = 1024;
 constexpr int kVecUnroll = 1;     // rows per thread per step in the vector kernels (measured best)
 
@@ -310,126 +311,130 @@ __device__ __forceinline__ void store_partials(const double *s_part, int W, doub
     if ((int)threadIdx.x < W) part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s_part[threadIdx.x];
 }
 
-// tot[w] = sum over b < nblk of part[w * nblk + b] in a fixed order, computed by
-// one workgroup of kFinThreads threads: thread t sums the strided subset
-// b = t % tpw (mod tpw) of value w = t / tpw (loads issued kFinUnroll at a
-// time, added in order), then thread w adds its tpw subtotals in order.
+// Finalize sums: for w < W1, tot[w] = sum over b < n1 of p1[w * n1 + b]; for
+// W1 <= w < W1 + W2 the same over p2 (n2 partials per value). One workgroup
+// of kFinThreads threads: value w is taken by tpw consecutive threads (tpw a
+// power of two of at most 64, so they share a wavefront); thread `sub` adds
+// partials sub, sub + tpw, ... in order (loads issued kFinUnroll at a time),
+// and a fixed xor-shuffle tree adds the tpw subtotals. Deterministic.
 constexpr int kFinUnroll = 16;
 
-__device__ void fin_sum(const double *__restrict__ part, int nblk, int W, double *scr,
-                        double *tot) {
-    const int t = threadIdx.x;
-    const int tpw = kFinThreads / W;
-    const int w = t / tpw, sub = t % tpw;
+__device__ void fin_sum2(const double *__restrict__ p1, int n1, int W1,
+                         const double *__restrict__ p2, int n2, int W2, double *tot) {
+    const int W = W1 + W2;
+    int tpw = 64;
+    while (tpw > 1 && tpw * W > kFinThreads) tpw >>= 1;
+    const int t = threadIdx.x, w = t / tpw, sub = t % tpw;
     double s = 0.0;
     if (w < W) {
-        for (int b0 = sub; b0 < nblk; b0 += tpw * kFinUnroll) {
+        const double *src = w < W1 ? p1 + (size_t)w * n1 : p2 + (size_t)(w - W1) * n2;
+        const int n = w < W1 ? n1 : n2;
+        for (int b0 = sub; b0 < n; b0 += tpw * kFinUnroll) {
             double v[kFinUnroll];
 #pragma unroll
             for (int u = 0; u < kFinUnroll; ++u) {
                 const int b = b0 + u * tpw;
-                v[u] = b < nblk ? part[(size_t)w * nblk + b] : 0.0;
+                v[u] = b < n ? src[b] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < kFinUnroll; ++u) s += v[u];
         }
     }
-    scr[t] = s;
-    __syncthreads();
-    if (t < W) {
-        double a = 0.0;
-        for (int j = 0; j < tpw; ++j) a += scr[t * tpw + j];
-        tot[t] = a;
-    }
+    for (int off = 1; off < tpw; off <<= 1) s += __shfl_xor(s, off);
+    if (sub == 0 && w < W) tot[w] = s;
     __syncthreads();
 }
 
-// Per-column workgroup partials of per-lane values: column c lives in lanes
-// whose index within their group of G lanes is c.
-__device__ __forceinline__ void column_partials(const double *vals, int nval, int k, int G,
+__device__ __forceinline__ void fin_sum(const double *__restrict__ part, int nblk, int W,
+                                        double *tot) {
+    fin_sum2(part, nblk, W, nullptr, 0, 0, tot);
+}
+
+// Per-column sums over the workgroup of `nval` per-lane values (lanes with
+// act = false give 0). Column c lives in the lanes whose index modulo CW is c
+// (CW a power of two: KP in the vector kernels, the lane-group width G in the
+// SpMM kernels), and c < k <= CW. Each wavefront adds its lanes of a column
+// with a fixed xor-shuffle tree; thread v * k + c then adds the wavefronts'
+// sums in wavefront order into s_part[v * k + c]. s_red holds
+// red_scratch(blockDim.x, nval) doubles.
+__host__ __device__ constexpr int red_scratch(int bt, int nval) { return (bt / 64) * nval * kMaxK; }
+
+__device__ __forceinline__ void column_partials(const double *vals, int nval, int k, int CW,
                                                 bool act, double *s_red, double *s_part) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int v = 0; v < nval; ++v) {
-        __syncthreads();
-        s_red[threadIdx.x] = act ? vals[v] : 0.0;
-        __syncthreads();
-        if ((int)threadIdx.x < k) {
-            double a = 0.0;
-            for (int t = threadIdx.x; t < T; t += G) a += s_red[t];
-            s_part[v * k + threadIdx.x] = a;
-        }
+        double x = act ? vals[v] : 0.0;
+        for (int off = CW; off < 64; off <<= 1) x += __shfl_xor(x, off);
+        if (lane < k) s_red[(wv * nval + v) * k + lane] = x;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < nval * k) {
+        const int v = t / k, c = t % k;
+        double a = 0.0;
+        for (int w = 0; w < nw; ++w) a += s_red[(w * nval + v) * k + c];
+        s_part[v * k + c] = a;
     }
     __syncthreads();
 }
 
 // ------------------------------------------------------------------ SpMM
 
-// RU rows of (alpha M + beta K) x for the calling group of G lanes, all
-// loads of the RU rows issued together. ok[u] = false rows yield 0. The
-// results are meaningful in lanes lane < KP with lane < k.
-template <typename R, int G, int KP, bool MASK, int RU>
-__device__ __forceinline__ void rows_core(const int32_t *__restrict__ rowptr,
-                                          const int32_t *__restrict__ col,
-                                          const R *__restrict__ K, const R *__restrict__ M,
-                                          R alpha, R beta, const uint8_t *__restrict__ mask,
-                                          const R *__restrict__ x, const int32_t (&i)[RU],
-                                          const bool (&ok)[RU], int k, int lane, int gbase,
-                                          R (&acc)[RU]) {
+// One row of (alpha M + beta K) x for the calling group of G lanes: row i,
+// CSR entries [rb, rb + len), dterm = alpha M_i added on the diagonal entry.
+// The group loads up to G entries at once (one per lane); every lane then
+// takes the entries of its part (NP = G / KP parts) from its neighbours by
+// cross-lane shuffles and gathers x for its column c = lane % KP, issuing the
+// gathers of up to 8 entries before using any. An entry a lane does not use
+// (past the row's end, or a masked column) gathers x[i, c] with coefficient
+// 0. The result is meaningful in lanes lane < KP with lane < k. With NP = 1,
+// *xi (if given) receives x[i, c], taken from the diagonal entry's gather.
+template <typename R, int G, int KP, bool MASK>
+__device__ __forceinline__ R row_apply(const int32_t *__restrict__ col, const R *__restrict__ K,
+                                       R beta, R dterm, const uint8_t *__restrict__ mask,
+                                       const R *__restrict__ x, int32_t i, int32_t rb,
+                                       int32_t len, int k, int lane, int gbase, R *xi) {
     constexpr int NP = G / KP;
+    constexpr int CH = KP < 8 ? KP : 8;  // gathers issued together
     const int c = lane % KP, part = lane / KP;
     const int cc = c < k ? c : k - 1;
-    int32_t rb[RU], re[RU];
-    R dterm[RU];
-    int32_t len = 0;
-#pragma unroll
-    for (int u = 0; u < RU; ++u) {
-        rb[u] = ok[u] ? rowptr[i[u]] : 0;
-        re[u] = ok[u] ? rowptr[i[u] + 1] : 0;
-        dterm[u] = ok[u] ? alpha * M[i[u]] : R(0);
-        len = max(len, re[u] - rb[u]);
-        acc[u] = 0;
-    }
+    R acc = 0, self = 0;
     for (int32_t e0 = 0; e0 < len; e0 += G) {
-        int32_t cj[RU];
-        R aj[RU];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int32_t e = rb[u] + e0 + lane;
-            cj[u] = 0;
-            aj[u] = 0;
-            if (e < re[u]) {
-                const int32_t j = col[e];
-                if (!MASK || !mask[j]) {
-                    cj[u] = j;
-                    aj[u] = beta * K[e];
-                    if (j == i[u]) aj[u] += dterm[u];
-                }
+        int32_t cj = i;
+        R aj = 0;
+        if (e0 + lane < len) {
+            const int32_t e = rb + e0 + lane;
+            const int32_t j = col[e];
+            if (!MASK || !mask[j]) {
+                cj = j;
+                aj = beta * K[e];
+                if (j == i) aj += dterm;
             }
         }
         if (KP == 1) {
-#pragma unroll
-            for (int u = 0; u < RU; ++u) acc[u] += aj[u] * x[cj[u]];
+            acc += aj * x[cj];
         } else {
 #pragma unroll
-            for (int u = 0; u < RU; ++u) {
+            for (int s0 = 0; s0 < KP; s0 += CH) {
+                int32_t js[CH];
+                R xv[CH];
 #pragma unroll
-                for (int s = 0; s < KP; ++s) {
-                    const int t = s * NP + part;
-                    const int32_t j = __shfl(cj[u], gbase + t);
-                    const R a = __shfl(aj[u], gbase + t);
-                    acc[u] += a * x[(int64_t)j * k + cc];
+                for (int s = 0; s < CH; ++s) js[s] = __shfl(cj, gbase + (s0 + s) * NP + part);
+#pragma unroll
+                for (int s = 0; s < CH; ++s) xv[s] = x[(int64_t)js[s] * k + cc];
+#pragma unroll
+                for (int s = 0; s < CH; ++s) {
+                    acc += __shfl(aj, gbase + (s0 + s) * NP + part) * xv[s];
+                    if (NP == 1 && js[s] == i) self = xv[s];
                 }
             }
         }
     }
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-#pragma unroll
-        for (int off = G / 2; off >= KP; off /= 2) acc[u] += __shfl_down(acc[u], off, G);
-    }
+    for (int off = G / 2; off >= KP; off /= 2) acc += __shfl_down(acc, off, G);
+    if (xi) *xi = self;
+    return acc;
 }
-
-// Rows handled together by one lane group.
-constexpr int kRowsInFlight = 1;
 
 // Lane layout of the vector kernels: KP lanes per row, lane c owns column c.
 struct VLane {
@@ -443,15 +448,41 @@ __device__ __forceinline__ VLane vlane(int k, int KP) {
     v.c = threadIdx.x % KP;
     v.act = v.c < k;
     v.grp = threadIdx.x / KP;
-    v.gpb = T / KP;
+    v.gpb = (int)blockDim.x / KP;
     return v;
 }
 
 
-enum FinMode { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUT = 3 };
+enum FinMode {
+    FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUT = 3,  // two reductions per iteration
+    FIN_SR_INIT = 4, FIN_SR_ITER = 5                         // one reduction per iteration
+};
 
+// Values per column in the (first) partial-sum array of a finalize mode; the
+// one-reduction modes read a second array of k values (w.z).
 __host__ __device__ inline int fin_width(int mode, int k) {
-    return (mode == FIN_INIT ? 3 : (mode == FIN_BETA ? 2 : 1)) * k;
+    return (mode == FIN_INIT || mode == FIN_SR_INIT ? 3
+                                                     : (mode == FIN_BETA || mode == FIN_SR_ITER ? 2 : 1)) *
+           k;
+}
+
+// Stopping tests after an iteration that produced residual norm^2 rr.
+__device__ inline void cg_stop_tests(CgCol &s, double rr, const CgParams &prm) {
+    if (rr < s.best) {
+        s.best = rr;
+        s.since = 0;
+    } else {
+        s.since += 1;
+    }
+    if (!prm.fixed && sqrt(rr) <= prm.rtol * sqrt(s.bb)) {
+        s.converged = 1;
+        s.active = 0;
+    } else if (s.iters >= prm.max_iter) {
+        s.active = 0;
+    } else if (!prm.fixed && prm.stall > 0 && s.since >= prm.stall) {
+        s.stalled = 1;
+        s.active = 0;
+    }
 }
 
 // Per-column PCG state transitions from the reduced dots `tot` (layout as
@@ -485,22 +516,48 @@ __device__ inline void cg_state_update(int mode, CgCol &s, const double *tot, in
         s.rz = rz_new;
         s.rr = rr;
         s.iters += 1;
-        if (rr < s.best) {
-            s.best = rr;
-            s.since = 0;
-        } else {
-            s.since += 1;
-        }
-        if (!prm.fixed && sqrt(rr) <= prm.rtol * sqrt(s.bb)) {
-            s.converged = 1;
-            s.active = 0;
-        } else if (s.iters >= prm.max_iter) {
-            s.active = 0;
-        } else if (!prm.fixed && prm.stall > 0 && s.since >= prm.stall) {
-            s.stalled = 1;
-            s.active = 0;
-        }
+        cg_stop_tests(s, rr, prm);
     }
+}
+
+// One-reduction PCG (Chronopoulos and Gear's rearrangement of the same
+// iteration): every iteration needs gamma = r.z, rho = r.r and delta = w.z,
+// w = A z, z = D^-1 r, all of one residual, so they are reduced together:
+//   beta_i = gamma_i / gamma_{i-1},
+//   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
+// (alpha_0 = gamma_0 / delta_0, beta_0 = 0). The vector update then forms
+// p = z + beta p and s = w + beta s (s = A p), x += alpha p, r -= alpha s.
+//   FIN_SR_INIT: tot = [r.z | r.r | b.b], tot2 = [w.z]
+//   FIN_SR_ITER: tot = [r.z | r.r],       tot2 = [w.z]  (after one update)
+__device__ inline void cg_sr_update(int mode, CgCol &s, const double *tot, const double *tot2,
+                                    int c, int k, const CgParams &prm) {
+    const double g = tot[c], rr = tot[k + c], dl = tot2[c];
+    if (mode == FIN_SR_INIT) {
+        s.bb = tot[2 * k + c];
+        s.rr = rr;
+        s.best = rr;
+        s.iters = 0;
+        s.since = 0;
+        s.stalled = 0;
+        const bool conv = !prm.fixed && sqrt(rr) <= prm.rtol * sqrt(s.bb);
+        s.converged = conv ? 1 : 0;
+        s.active = (!conv && prm.max_iter > 0) ? 1 : 0;
+        s.rz = g;
+        s.pq = dl;
+        s.beta = 0.0;
+        s.alpha = (s.active && dl != 0.0) ? g / dl : 0.0;
+        return;
+    }
+    if (!s.active) return;
+    s.iters += 1;
+    s.rr = rr;
+    cg_stop_tests(s, rr, prm);
+    const double bt = s.rz != 0.0 ? g / s.rz : 0.0;
+    const double den = dl - (s.alpha != 0.0 ? bt * g / s.alpha : 0.0);
+    s.beta = bt;
+    s.pq = den;
+    s.alpha = den != 0.0 ? g / den : 0.0;
+    s.rz = g;
 }
 
 }  // namespace kern

@@ -84,7 +84,7 @@ ks_assemble(const SrvHdr *hdr, const SrvDesc *d, int32_t *ndeg) {
 __global__ void __launch_bounds__(T)
 ks_init(const SrvHdr *hdr, const SrvDesc *d, R alpha, R beta) {
     __shared__ double s_part[3 * kSrvMaxK];
-    __shared__ double s_red[T];
+    __shared__ double s_red[red_scratch(T, 3)];
     const int n = hdr->n, tot = hdr->tot_v;
     for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
         const SrvDesc &q = d[find_req(d, n, v, SP_V)];
@@ -122,17 +122,20 @@ __device__ __forceinline__ void spmm_tile(const SrvDesc &q, int32_t tile, R alph
     const int lane = threadIdx.x % G, grp = threadIdx.x / G;
     const int gbase = (threadIdx.x & 63) - lane;
     const int32_t row = tile * GPB + grp;
-    const int32_t i[1] = {row < q.view.nV ? row : 0};
-    const bool ok[1] = {row < q.view.nV};
-    R acc[1];
-    rows_core<R, G, KP, false, 1>(q.view.rowptr, q.view.col, q.K, q.M, alpha, beta, nullptr, q.p, i,
-                                  ok, q.k, lane, gbase, acc);
-    const bool out = ok[0] && lane < q.k && lane < KP;
+    const bool ok = row < q.view.nV;
+    R acc = 0, pi = 0;
+    if (ok) {
+        const int32_t rb = q.view.rowptr[row];
+        acc = row_apply<R, G, KP, false>(q.view.col, q.K, beta, alpha * q.M[row], nullptr, q.p, row,
+                                         rb, q.view.rowptr[row + 1] - rb, q.k, lane, gbase, &pi);
+    }
+    const bool out = ok && lane < q.k && lane < KP;
     double ds = 0.0;
     if (out) {
         const int64_t e = (int64_t)row * q.k + lane;
-        q.q[e] = acc[0];
-        ds = (double)q.p[e] * (double)acc[0];
+        q.q[e] = acc;
+        if (G != KP) pi = q.p[e];  // row_apply returns p[i, c] only when G == KP
+        ds = (double)pi * (double)acc;
     }
     column_partials(&ds, 1, q.k, G, out, s_red, s_part);
     if ((int)threadIdx.x < q.k) q.part[(size_t)threadIdx.x * q.tiles_s + tile] = s_part[threadIdx.x];
@@ -143,7 +146,7 @@ __device__ __forceinline__ void spmm_tile(const SrvDesc &q, int32_t tile, R alph
 __global__ void __launch_bounds__(T)
 ks_spmm(const SrvHdr *hdr, const SrvDesc *d, int j, R alpha, R beta) {
     __shared__ double s_part[kSrvMaxK];
-    __shared__ double s_red[T];
+    __shared__ double s_red[red_scratch(T, 1)];
     const int n = hdr->n, tot = hdr->tot_s;
     for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
         const SrvDesc &q = d[find_req(d, n, v, SP_S)];
@@ -163,13 +166,12 @@ ks_spmm(const SrvHdr *hdr, const SrvDesc *d, int j, R alpha, R beta) {
 template <int MODE>
 __global__ void __launch_bounds__(kFinThreads)
 ks_fin(const SrvHdr *hdr, const SrvDesc *d, int j, CgParams prm) {
-    __shared__ double s_scr[kFinThreads];
     __shared__ double s_tot[3 * kSrvMaxK];
     for (int r = blockIdx.x; r < hdr->n; r += gridDim.x) {
         const SrvDesc &q = d[r];
         if (MODE == FIN_INIT ? !q.init : j >= q.iters) continue;
         const int nt = MODE == FIN_ALPHA ? q.tiles_s : q.tiles_v;
-        fin_sum(q.part, nt, fin_width(MODE, q.k), s_scr, s_tot);
+        fin_sum(q.part, nt, fin_width(MODE, q.k), s_tot);
         if ((int)threadIdx.x < q.k) cg_state_update(MODE, q.st[threadIdx.x], s_tot, threadIdx.x, q.k, prm);
         __syncthreads();
     }
@@ -179,7 +181,7 @@ ks_fin(const SrvHdr *hdr, const SrvDesc *d, int j, CgParams prm) {
 __global__ void __launch_bounds__(T)
 ks_update(const SrvHdr *hdr, const SrvDesc *d, int j) {
     __shared__ double s_part[2 * kSrvMaxK];
-    __shared__ double s_red[T];
+    __shared__ double s_red[red_scratch(T, 2)];
     const int n = hdr->n, tot = hdr->tot_v;
     for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
         const SrvDesc &q = d[find_req(d, n, v, SP_V)];
@@ -250,9 +252,9 @@ int64_t footprint_of(int32_t nV, int64_t nF, int32_t k, bool per_mesh_path) {
     if (per_mesh_path) {
         // the per-mesh PCG workspace (grown once, with headroom) and the
         // assembly counter
-        const int64_t ws = 4 * rnd(4 * (int64_t)nV * k) + rnd(4 * (int64_t)nV) +
-                           rnd(8 * 1024 * 3 * 64) + rnd(80 * 64) + rnd(8 * 64) + 4096;
+        const int64_t ws = (int64_t)pcg_layout(nV, nnz, k, sizeof(float)).total;
         b += rnd(ws + ws / 4) + rnd(320);
+        b += rnd(8 * (int64_t)nV) + rnd(nV);  // SpMV row descriptors
     }
     return b + 8192;
 }
@@ -330,7 +332,11 @@ class GpuExec {
         DGO_HIP(hipMemcpyAsync(dX, in.h_X, 12 * nV, hipMemcpyHostToDevice, ps));
         DGO_HIP(hipMemcpyAsync(df, in.h_f, 4 * nV * k, hipMemcpyHostToDevice, ps));
         dgo_allocator al{bump_alloc, bump_free, &rd->bump};
-        dgo_status st = dgo_mesh_create(2, in.nV, in.nF, dF, &al, (dgo_stream)ps, &rd->mesh);
+        // the batched kernels read the CSR directly; the one-at-a-time
+        // baseline goes through the SpMV entry points, which need row
+        // descriptors (natural order: no host-side reordering per request)
+        dgo_status st = mesh_create(2, in.nV, in.nF, dF, &al, ps,
+                                    o_.batched ? ROWS_NONE : ROWS_NATURAL, &rd->mesh);
         if (st != DGO_OK) return st;
         dgo_mesh *m = rd->mesh;
         SrvDesc &D = rd->desc;

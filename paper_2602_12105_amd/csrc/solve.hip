@@ -9,23 +9,26 @@
 // shuffles and gathers x for its column c = lane % KP; the gathers of one
 // chunk are independent, so they are all in flight together. Parts are
 // combined by a fixed shuffle tree. The operator alpha M + beta K is never
-// formed: the mass term is added on the diagonal entry.
+// formed: the mass term is added on the diagonal entry. Rows are visited in
+// the mesh's breadth-first row order when it has one (large meshes), so that
+// each XCD's contiguous share of rows gathers mostly x rows of its own share.
 //
-// PCG (Saad, Alg. 9.1, Jacobi preconditioner) runs three kernels per
-// iteration:
-//   1. q = A p, fused with the dot p.q; the last workgroup sets alpha;
-//   2. r -= alpha q with z = D^-1 r formed on the fly, fused with the dots
-//      r.z and r.r; the last workgroup sets beta and tests for stopping;
-//   3. x += alpha p and p = D^-1 r + beta p in one pass.
-// Vectors streamed per iteration: p (gather) and q in 1; r, q and r in 2;
-// x, p, r, x and p in 3. Every dot is reduced in a fixed order: each
-// workgroup stores its per-column partial sums with plain stores, and a
-// one-workgroup finalize kernel launched right after adds them in a fixed
-// order and updates the per-column scalars. The kernel boundary orders the
-// partials before the finalize kernel reads them, so no device-scope fence
-// is issued per workgroup (each such fence writes back the XCD's L2). The
-// result is bitwise deterministic run to run. Columns stop independently and
-// are frozen once stopped.
+// PCG: Jacobi-preconditioned conjugate gradients (Saad, Alg. 9.1) in the
+// one-reduction arrangement of Chronopoulos and Gear: the recurrence s = A p
+// is carried along, so that the three dots an iteration needs (r.z, r.r of the
+// new residual and w.z with w = A z) belong to one residual and are reduced
+// together. An iteration is three kernels:
+//   1. vector update p = z + beta p, s = w + beta s, x += alpha p,
+//      r -= alpha s, with partial sums of r.z and r.r (z = D^-1 r);
+//   2. w = A z, fused with partial sums of w.z; A z is one sweep over the
+//      values v_ij = A_ij d_j prepared once per solve (d = D^-1);
+//   3. a one-workgroup finalize: beta, alpha and the stopping tests.
+// Every dot is reduced in a fixed order: each workgroup stores its
+// per-column partial sums with plain stores and the finalize kernel adds
+// them in a fixed order; the kernel boundary orders the stores before the
+// reads, so no device-scope fence is issued per workgroup (each such fence
+// writes back the XCD's L2). Results are bitwise deterministic run to run.
+// Columns stop independently and are frozen once stopped.
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -38,14 +41,17 @@ namespace {
 
 using namespace kern;
 
+// Rows are taken in the mesh's row order: position r holds row i = rdesc[r].x
+// whose entries start at rdesc[r].y, rlen[r] of them (one load level instead
+// of order -> row pointers).
 template <typename R, int KP>
-__global__ void __launch_bounds__(T)
-k_spmm(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, int32_t nV, int64_t nnz,
-       R alpha, const R *__restrict__ M, R beta, const R *__restrict__ K, int k,
-       const R *__restrict__ x, R *__restrict__ y) {
+__global__ void __launch_bounds__(T, KP <= 16 ? 8 : 4)
+k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
+       const int32_t *__restrict__ col, int32_t nV, int64_t nnz, R alpha,
+       const R *__restrict__ M, R beta, const R *__restrict__ K, int k, const R *__restrict__ x,
+       R *__restrict__ y) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = T / G;
-    constexpr int RU = kRowsInFlight;
     const int64_t bt = blockIdx.y;
     M += bt * nV;
     K += bt * nnz;
@@ -55,71 +61,53 @@ k_spmm(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, int3
     const int gbase = (threadIdx.x & 63) - lane;
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
-    for (int64_t tile = t0; tile < t1; tile += RU) {
-        int32_t i[RU];
-        bool ok[RU];
-        bool any = false;
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t r = (tile + u) * GPB + grp;
-            ok[u] = tile + u < t1 && r < nV;
-            i[u] = ok[u] ? (int32_t)r : 0;
-            any = any || ok[u];
-        }
-        if (!any) continue;
-        R acc[RU];
-        rows_core<R, G, KP, false, RU>(rowptr, col, K, M, alpha, beta, nullptr, x, i, ok, k, lane,
-                                       gbase, acc);
-#pragma unroll
-        for (int u = 0; u < RU; ++u)
-            if (ok[u] && lane < k && lane < KP) y[(int64_t)i[u] * k + lane] = acc[u];
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t r = tile * GPB + grp;
+        if (r >= nV) continue;  // uniform over the lane group
+        const int2 d = rdesc[r];
+        const int32_t len = rlen[r];
+        const R acc = row_apply<R, G, KP, false>(col, K, beta, alpha * M[d.x], nullptr, x, d.x,
+                                                 d.y, len, k, lane, gbase, nullptr);
+        if (lane < k && lane < KP) y[(int64_t)d.x * k + lane] = acc;
     }
 }
 
 // ------------------------------------------------------------------- PCG
 
-// q = A_II p (q_B = 0). With part != NULL also stores per-column partial sums
-// of p.q (finished by k_cg_fin<FIN_ALPHA>).
+// q = A_II p (q_B = 0), from M and K (A x0 at the start of a solve). With
+// part != NULL also stores per-column partial sums of p.q.
 template <typename R, int KP, bool MASK>
-__global__ void __launch_bounds__(T)
-k_cg_spmm_dot(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, int32_t nV,
-              R alpha_m, const R *__restrict__ M, R beta_k, const R *__restrict__ K,
-              const uint8_t *__restrict__ mask, int k, const R *__restrict__ p, R *__restrict__ q,
-              double *__restrict__ part) {
+__global__ void __launch_bounds__(T, KP <= 16 ? 8 : 4)
+k_cg_spmm_dot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
+              const int32_t *__restrict__ col, int32_t nV, R alpha_m, const R *__restrict__ M,
+              R beta_k, const R *__restrict__ K, const uint8_t *__restrict__ mask, int k,
+              const R *__restrict__ p, R *__restrict__ q, double *__restrict__ part) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = T / G;
     __shared__ double s_part[kMaxK];
-    __shared__ double s_red[T];
+    __shared__ double s_red[red_scratch(T, 1)];
     const int lane = threadIdx.x % G, grp = threadIdx.x / G;
     const int gbase = (threadIdx.x & 63) - lane;
     const bool out_lane = lane < k && lane < KP;
-    constexpr int RU = kRowsInFlight;
     double dsum = 0.0;
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
-    for (int64_t tile = t0; tile < t1; tile += RU) {
-        int32_t i[RU];
-        bool ok[RU], row[RU];
-        bool any = false;
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t r = (tile + u) * GPB + grp;
-            row[u] = tile + u < t1 && r < nV;
-            i[u] = row[u] ? (int32_t)r : 0;
-            ok[u] = row[u] && !(MASK && mask[i[u]]);
-            any = any || row[u];
-        }
-        if (!any) continue;
-        R acc[RU];
-        rows_core<R, G, KP, MASK, RU>(rowptr, col, K, M, alpha_m, beta_k, mask, p, i, ok, k, lane,
-                                      gbase, acc);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t r = tile * GPB + grp;
+        if (r >= nV) continue;  // uniform over the lane group
+        const int2 d = rdesc[r];
+        const int32_t i = d.x;
+        const int32_t len = rlen[r];
+        R acc = 0, pi = 0;
+        if (!(MASK && mask[i]))
+            acc = row_apply<R, G, KP, MASK>(col, K, beta_k, alpha_m * M[i], mask, p, i, d.y, len,
+                                            k, lane, gbase, &pi);
         if (out_lane) {
-#pragma unroll
-            for (int u = 0; u < RU; ++u) {
-                if (!row[u]) continue;
-                const int64_t e = (int64_t)i[u] * k + lane;
-                q[e] = acc[u];
-                if (part) dsum += (double)p[e] * (double)acc[u];
+            const int64_t e = (int64_t)i * k + lane;
+            q[e] = acc;
+            if (part) {
+                if (G != KP) pi = p[e];  // row_apply returns p[i, c] only when G == KP
+                dsum += (double)pi * (double)acc;
             }
         }
     }
@@ -128,14 +116,14 @@ k_cg_spmm_dot(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ co
     store_partials(s_part, k, part);
 }
 
-// r = beff - q, p = D^-1 r; partial sums of r.z, r.r, beff.beff.
+// r = beff - q, p = s = 0; partial sums of r.z, r.r, beff.beff (z = D^-1 r).
 template <typename R>
-__global__ void __launch_bounds__(T)
+__global__ void __launch_bounds__(TR)
 k_cg_init(int32_t nV, int k, int KP, const R *__restrict__ beff, const R *__restrict__ q,
-          const R *__restrict__ invD, R *__restrict__ r, R *__restrict__ p,
+          const R *__restrict__ invD, R *__restrict__ r, R *__restrict__ p, R *__restrict__ sv,
           double *__restrict__ part) {
     __shared__ double s_part[3 * kMaxK];
-    __shared__ double s_red[T];
+    __shared__ double s_red[red_scratch(TR, 3)];
     const VLane L = vlane(k, KP);
     double d[3] = {0.0, 0.0, 0.0};
     int64_t t0, t1;
@@ -148,7 +136,8 @@ k_cg_init(int32_t nV, int k, int KP, const R *__restrict__ beff, const R *__rest
         const R rv = b - q[e];
         const R zv = invD[i] * rv;
         r[e] = rv;
-        p[e] = zv;
+        p[e] = R(0);
+        sv[e] = R(0);
         d[0] += (double)rv * (double)zv;
         d[1] += (double)rv * (double)rv;
         d[2] += (double)b * (double)b;
@@ -157,101 +146,125 @@ k_cg_init(int32_t nV, int k, int KP, const R *__restrict__ beff, const R *__rest
     store_partials(s_part, 3 * k, part);
 }
 
-// r -= alpha q on active columns; partial sums of r.z (z = D^-1 r) and r.r.
+// The operator's values scaled by the preconditioner, v_ij = A_ij d_j with
+// A = alpha M + beta K and d = D^-1 (d is zero on masked rows, so masked
+// columns drop out), and v = 0 on masked rows. Prepared once per solve, so
+// that w = A D^-1 r is one sweep over v with no per-entry scaling.
 template <typename R>
-__global__ void __launch_bounds__(T)
-k_cg_update(int32_t nV, int k, int KP, R *__restrict__ r, const R *__restrict__ q,
-            const R *__restrict__ invD, const CgCol *__restrict__ st, double *__restrict__ part) {
+__global__ void k_cg_values(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                            int32_t nV, R alpha, const R *__restrict__ M, R beta,
+                            const R *__restrict__ K, const uint8_t *__restrict__ mask,
+                            const R *__restrict__ invD, R *__restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= nV) return;
+    const bool masked = mask && mask[i];
+    const R dm = alpha * M[i];
+    for (int32_t t = rowptr[i]; t < rowptr[i + 1]; ++t) {
+        const int32_t j = col[t];
+        R a = beta * K[t];
+        if (j == i) a += dm;
+        v[t] = masked ? R(0) : a * invD[j];
+    }
+}
+
+// w = A_II z with z = D^-1 r, as w_i = sum_j v_ij r_j, fused with per-column
+// partial sums of w.z. Rows in the mesh's row order (as k_spmm).
+template <typename R, int KP>
+__global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
+k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
+          const int32_t *__restrict__ col, int32_t nV, const R *__restrict__ v,
+          const R *__restrict__ invD, int k, const R *__restrict__ r, R *__restrict__ w,
+          double *__restrict__ part) {
+    constexpr int G = KP < 8 ? 8 : KP;
+    constexpr int GPB = TR / G;
+    __shared__ double s_part[kMaxK];
+    __shared__ double s_red[red_scratch(TR, 1)];
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int gbase = (threadIdx.x & 63) - lane;
+    const bool out_lane = lane < k && lane < KP;
+    double dsum = 0.0;
+    int64_t t0, t1;
+    tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t pos = tile * GPB + grp;
+        if (pos >= nV) continue;  // uniform over the lane group
+        const int2 d = rdesc[pos];
+        const int32_t i = d.x;
+        const int32_t len = rlen[pos];
+        const R di = invD[i];
+        R ri = 0;
+        const R acc = row_apply<R, G, KP, false>(col, v, R(1), R(0), nullptr, r, i, d.y, len, k,
+                                                 lane, gbase, &ri);
+        if (out_lane) {
+            const int64_t e = (int64_t)i * k + lane;
+            w[e] = acc;
+            if (G != KP) ri = r[e];  // row_apply returns r[i, c] only when G == KP
+            dsum += (double)acc * (double)(di * ri);
+        }
+    }
+    column_partials(&dsum, 1, k, G, out_lane, s_red, s_part);
+    store_partials(s_part, k, part);
+}
+
+// The vector work of one iteration on the active columns: p = z + beta p,
+// s = w + beta s, x += alpha p, r -= alpha s (z = D^-1 r), fused with partial
+// sums of r.z and r.r of the new residual.
+template <typename R>
+__global__ void __launch_bounds__(TR)
+k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R *__restrict__ p,
+             R *__restrict__ sv, const R *__restrict__ w, const R *__restrict__ invD,
+             const CgCol *__restrict__ st, double *__restrict__ part) {
     __shared__ double s_part[2 * kMaxK];
-    __shared__ double s_red[T];
+    __shared__ double s_red[red_scratch(TR, 2)];
     const VLane L = vlane(k, KP);
     const bool on = L.act && st[L.c].active;
-    const R a = on ? (R)st[L.c].alpha : R(0);
+    const R a = on ? (R)st[L.c].alpha : R(0), bt = on ? (R)st[L.c].beta : R(0);
     double d[2] = {0.0, 0.0};
     int64_t t0, t1;
     tile_range(((int64_t)nV + L.gpb - 1) / L.gpb, t0, t1);
     if (on) {
-        // kVecUnroll rows per thread at a time, all loads issued first
-        for (int64_t tb = t0; tb < t1; tb += kVecUnroll) {
-            R rv[kVecUnroll], qv[kVecUnroll], dv[kVecUnroll];
-#pragma unroll
-            for (int u = 0; u < kVecUnroll; ++u) {
-                const int64_t i = (tb + u) * L.gpb + L.grp;
-                const bool ok = tb + u < t1 && i < nV;
-                const int64_t e = ok ? i * k + L.c : 0;
-                rv[u] = ok ? r[e] : R(0);
-                qv[u] = ok ? q[e] : R(0);
-                dv[u] = ok ? invD[i] : R(0);
-            }
-#pragma unroll
-            for (int u = 0; u < kVecUnroll; ++u) {
-                const int64_t i = (tb + u) * L.gpb + L.grp;
-                if (!(tb + u < t1 && i < nV)) continue;
-                const R nr = rv[u] - a * qv[u];
-                const R zv = dv[u] * nr;
-                r[i * k + L.c] = nr;
-                d[0] += (double)nr * (double)zv;
-                d[1] += (double)nr * (double)nr;
-            }
+        for (int64_t tile = t0; tile < t1; ++tile) {
+            const int64_t i = tile * L.gpb + L.grp;
+            if (i >= nV) continue;
+            const int64_t e = i * k + L.c;
+            const R rv = r[e], wv = w[e], pv = p[e], s0 = sv[e], xv = x[e], dv = invD[i];
+            const R pn = dv * rv + bt * pv;
+            const R sn = wv + bt * s0;
+            const R rn = rv - a * sn;
+            p[e] = pn;
+            sv[e] = sn;
+            x[e] = xv + a * pn;
+            r[e] = rn;
+            const R zn = dv * rn;
+            d[0] += (double)rn * (double)zn;
+            d[1] += (double)rn * (double)rn;
         }
     }
     column_partials(d, 2, k, KP, on, s_red, s_part);
     store_partials(s_part, 2 * k, part);
 }
 
-// x += alpha p for the columns updated in this iteration (alpha != 0), and
-// p = D^-1 r + beta p for the columns still active.
-template <typename R>
-__global__ void __launch_bounds__(T)
-k_cg_pupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ p,
-             const R *__restrict__ r, const R *__restrict__ invD, const CgCol *st) {
-    const VLane L = vlane(k, KP);
-    if (!L.act) return;
-    const double ad = st[L.c].alpha;
-    const bool act = st[L.c].active;
-    if (ad == 0.0 && !act) return;
-    const R a = (R)ad, bt = (R)st[L.c].beta;
-    int64_t t0, t1;
-    tile_range(((int64_t)nV + L.gpb - 1) / L.gpb, t0, t1);
-    for (int64_t tb = t0; tb < t1; tb += kVecUnroll) {
-        R pv[kVecUnroll], xv[kVecUnroll], rv[kVecUnroll], dv[kVecUnroll];
-#pragma unroll
-        for (int u = 0; u < kVecUnroll; ++u) {
-            const int64_t i = (tb + u) * L.gpb + L.grp;
-            const bool ok = tb + u < t1 && i < nV;
-            const int64_t e = ok ? i * k + L.c : 0;
-            pv[u] = ok ? p[e] : R(0);
-            xv[u] = ok ? x[e] : R(0);
-            rv[u] = ok && act ? r[e] : R(0);
-            dv[u] = ok && act ? invD[i] : R(0);
-        }
-#pragma unroll
-        for (int u = 0; u < kVecUnroll; ++u) {
-            const int64_t i = (tb + u) * L.gpb + L.grp;
-            if (!(tb + u < t1 && i < nV)) continue;
-            const int64_t e = i * k + L.c;
-            x[e] = xv[u] + a * pv[u];
-            if (act) p[e] = dv[u] * rv[u] + bt * pv[u];
-        }
-    }
-}
-
-// One workgroup: add the partial sums of the preceding kernel in a fixed
-// order, then update the per-column state (or store the totals).
+// One workgroup: add the partial sums of the preceding kernel(s) in a fixed
+// order, then update the per-column state (or store the totals). The
+// one-reduction modes also add a second array of k values (w.z).
 template <int MODE>
 __global__ void __launch_bounds__(kFinThreads)
-k_cg_fin(const double *__restrict__ part, int nblk, int k, CgCol *st, CgParams prm,
-         double *out) {
-    __shared__ double s_scr[kFinThreads];
-    __shared__ double s_tot[3 * kMaxK];
-    fin_sum(part, nblk, fin_width(MODE, k), s_scr, s_tot);
+k_cg_fin(const double *__restrict__ part, int nblk, const double *__restrict__ part2, int nblk2,
+         int k, CgCol *st, CgParams prm, double *out) {
+    __shared__ double s_tot[4 * kMaxK];
+    constexpr bool SR = MODE == FIN_SR_INIT || MODE == FIN_SR_ITER;
+    const int W = fin_width(MODE, k);
+    fin_sum2(part, nblk, W, part2, nblk2, SR ? k : 0, s_tot);
     const int c = threadIdx.x;
     if (c >= k) return;
     if (MODE == FIN_OUT) {
         out[c] = s_tot[c];
         return;
     }
-    cg_state_update(MODE, st[c], s_tot, c, k, prm);
+    if (SR)
+        cg_sr_update(MODE, st[c], s_tot, s_tot + W, c, k, prm);
+    else
+        cg_state_update(MODE, st[c], s_tot, c, k, prm);
 }
 
 // 1 / (alpha M_ii + beta K_ii); zero on masked rows.
@@ -293,13 +306,13 @@ __global__ void k_cg_lift(const int32_t *__restrict__ rowptr, const int32_t *__r
 
 // Partial sums of ||beff - A_II u||^2 per column, accumulated in FP64.
 template <typename R>
-__global__ void __launch_bounds__(T)
+__global__ void __launch_bounds__(TR)
 k_cg_trueres(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col, int32_t nV,
              double alpha, const R *__restrict__ M, double beta, const R *__restrict__ K,
              const uint8_t *__restrict__ mask, int k, int KP, const R *__restrict__ beff,
              const R *__restrict__ u, double *__restrict__ part) {
     __shared__ double s_part[kMaxK];
-    __shared__ double s_red[T];
+    __shared__ double s_red[red_scratch(TR, 1)];
     const VLane L = vlane(k, KP);
     double d = 0.0;
     int64_t t0, t1;
@@ -336,8 +349,8 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
     constexpr int G = KP < 8 ? 8 : KP;
     dim3 grid(nblocks_for(ntiles(m->nV, T / G)), (unsigned)batch);
     DGO_LAUNCH("spmm", s,
-               k_spmm<R, KP><<<grid, T, 0, s>>>(m->rowptr, m->col, m->nV, m->nnz, alpha, M, beta, K,
-                                                k, x, y));
+               k_spmm<R, KP><<<grid, T, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV, m->nnz, alpha,
+                                                M, beta, K, k, x, y));
 }
 
 template <typename R>
@@ -361,8 +374,8 @@ int launch_cg_spmm_kp(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K
     constexpr int G = KP < 8 ? 8 : KP;
     const unsigned nb = nblocks_for(ntiles(m->nV, T / G), part ? kMaxRedBlocks : kMaxBlocks);
     DGO_LAUNCH("cg_spmm_dot", s,
-               k_cg_spmm_dot<R, KP, MASK><<<nb, T, 0, s>>>(m->rowptr, m->col, m->nV, alpha, M, beta,
-                                                           K, mask, k, p, q, part));
+               k_cg_spmm_dot<R, KP, MASK><<<nb, T, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV, alpha,
+                                                           M, beta, K, mask, k, p, q, part));
     return (int)nb;
 }
 
@@ -388,11 +401,59 @@ int launch_cg_spmm(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
 }
 
 template <int MODE>
-void launch_fin(const double *part, int nblk, int k, CgCol *st, CgParams prm, double *out,
-                hipStream_t s) {
+void launch_fin(const double *part, int nblk, const double *part2, int nblk2, int k, CgCol *st,
+                CgParams prm, double *out, hipStream_t s) {
     DGO_LAUNCH("cg_fin", s,
-               k_cg_fin<MODE><<<1, kFinThreads, 0, s>>>(part, nblk, k, st, prm, out));
+               k_cg_fin<MODE><<<1, kFinThreads, 0, s>>>(part, nblk, part2, nblk2, k, st, prm, out));
 }
+
+template <typename R, int KP>
+int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *invD, int k, const R *r, R *w,
+                   double *part, hipStream_t s) {
+    constexpr int G = KP < 8 ? 8 : KP;
+    const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), kMaxRedBlocks);
+    DGO_LAUNCH("cg_sdot", s,
+               k_cg_sdot<R, KP><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV, v, invD, k, r,
+                                                 w, part));
+    return (int)nb;
+}
+
+template <typename R>
+int launch_sdot(const dgo_mesh *m, const R *v, const R *invD, int k, const R *r, R *w,
+                double *part, hipStream_t s) {
+    switch (pow2ceil(k)) {
+        case 1: return launch_sdot_kp<R, 1>(m, v, invD, k, r, w, part, s);
+        case 2: return launch_sdot_kp<R, 2>(m, v, invD, k, r, w, part, s);
+        case 4: return launch_sdot_kp<R, 4>(m, v, invD, k, r, w, part, s);
+        case 8: return launch_sdot_kp<R, 8>(m, v, invD, k, r, w, part, s);
+        case 16: return launch_sdot_kp<R, 16>(m, v, invD, k, r, w, part, s);
+        case 32: return launch_sdot_kp<R, 32>(m, v, invD, k, r, w, part, s);
+        default: return launch_sdot_kp<R, 64>(m, v, invD, k, r, w, part, s);
+    }
+}
+
+}  // namespace
+
+PcgLayout pcg_layout(int64_t nV, int64_t nnz, int k, size_t elem) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t vec = al(elem * (size_t)nV * (size_t)k);
+    PcgLayout L;
+    L.off_r = 0;
+    L.off_p = vec;
+    L.off_s = 2 * vec;
+    L.off_w = 3 * vec;
+    L.off_b = 4 * vec;
+    L.off_d = 5 * vec;
+    L.off_v = L.off_d + al(elem * (size_t)nV);
+    L.off_pt = L.off_v + al(elem * (size_t)nnz);
+    L.off_pt2 = L.off_pt + al(sizeof(double) * kern::kMaxRedBlocks * 3 * kern::kMaxK);
+    L.off_st = L.off_pt2 + al(sizeof(double) * kern::kMaxRedBlocks * kern::kMaxK);
+    L.off_tr = L.off_st + al(sizeof(kern::CgCol) * kern::kMaxK);
+    L.total = L.off_tr + al(sizeof(double) * kern::kMaxK);
+    return L;
+}
+
+namespace {
 
 template <typename R>
 dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, const R *K,
@@ -400,22 +461,19 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
                    dgo_cg_report *rep, hipStream_t s) {
     const int64_t nV = m->nV, n = nV * k;
     const int KP = pow2ceil(k);
-    // workspace: r p q beff invD | partial sums | state | trueres
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t vec = al(sizeof(R) * (size_t)n);
-    const size_t off_r = 0, off_p = vec, off_q = 2 * vec, off_b = 3 * vec;
-    const size_t off_d = 4 * vec;
-    const size_t off_pt = off_d + al(sizeof(R) * (size_t)nV);
-    const size_t off_st = off_pt + al(sizeof(double) * kMaxRedBlocks * 3 * kMaxK);
-    const size_t off_tr = off_st + al(sizeof(CgCol) * kMaxK);
-    const size_t total = off_tr + al(sizeof(double) * kMaxK);
+    const PcgLayout L = pcg_layout(nV, m->nnz, k, sizeof(R));
+    const size_t off_r = L.off_r, off_p = L.off_p, off_s = L.off_s, off_w = L.off_w;
+    const size_t off_b = L.off_b, off_d = L.off_d, off_v = L.off_v, off_pt = L.off_pt;
+    const size_t off_pt2 = L.off_pt2, off_st = L.off_st, off_tr = L.off_tr, total = L.total;
     void *wsv;
     DGO_TRY(mesh_workspace(const_cast<dgo_mesh *>(m), total, s, &wsv));
     char *ws = (char *)wsv;
-    R *r = (R *)(ws + off_r), *p = (R *)(ws + off_p), *q = (R *)(ws + off_q);
+    R *r = (R *)(ws + off_r), *p = (R *)(ws + off_p), *sv = (R *)(ws + off_s);
+    R *w = (R *)(ws + off_w);
     R *beff = mask ? (R *)(ws + off_b) : const_cast<R *>(b);
     R *invD = (R *)(ws + off_d);
-    double *part = (double *)(ws + off_pt);
+    R *v = (R *)(ws + off_v);
+    double *part = (double *)(ws + off_pt), *part2 = (double *)(ws + off_pt2);
     CgCol *st = (CgCol *)(ws + off_st);
     double *tr = (double *)(ws + off_tr);
 
@@ -426,35 +484,37 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     prm.stall = o.stall_iters;
     prm.k = k;
 
-    const unsigned nb_v = nblocks_for(ntiles(nV, T / KP), kMaxRedBlocks);
-    const unsigned nb_p = nblocks_for(ntiles(nV, T / KP));
+    const unsigned nb_v = nblocks_for(ntiles(nV, TR / KP), kMaxRedBlocks);
     const R ra = (R)alpha, rb = (R)beta;
 
     DGO_LAUNCH("cg_invdiag", s,
                k_cg_invdiag<R><<<grid_for(nV, T), T, 0, s>>>((int32_t)nV, ra, M, rb, K, m->diag, mask,
                                                              invD));
+    DGO_LAUNCH("cg_values", s,
+               k_cg_values<R><<<grid_for(nV, T), T, 0, s>>>(m->rowptr, m->col, (int32_t)nV, ra, M, rb,
+                                                            K, mask, invD, v));
     if (mask)
         DGO_LAUNCH("cg_lift", s,
                    k_cg_lift<R><<<grid_for(n, T), T, 0, s>>>(m->rowptr, m->col, (int32_t)nV, ra, M, rb,
                                                              K, mask, k, b, g, beff, u));
-    // r0 = beff - A_II x0, z0 = D^-1 r0, p0 = z0
-    launch_cg_spmm<R>(m, ra, M, rb, K, mask, k, u, q, nullptr, s);
+    // r0 = beff - A_II x0, p = s = 0, w0 = A D^-1 r0; alpha_0 = (r.z) / (w.z)
+    launch_cg_spmm<R>(m, ra, M, rb, K, mask, k, u, w, nullptr, s);
     DGO_LAUNCH("cg_init", s,
-               k_cg_init<R><<<nb_v, T, 0, s>>>((int32_t)nV, k, KP, beff, q, invD, r, p, part));
-    launch_fin<FIN_INIT>(part, (int)nb_v, k, st, prm, nullptr, s);
+               k_cg_init<R><<<nb_v, TR, 0, s>>>((int32_t)nV, k, KP, beff, w, invD, r, p, sv, part));
+    int nb_s = launch_sdot<R>(m, v, invD, k, r, w, part2, s);
+    launch_fin<FIN_SR_INIT>(part, (int)nb_v, part2, nb_s, k, st, prm, nullptr, s);
     DGO_HIP(hipGetLastError());
 
     const int every = o.fixed_iters ? (o.max_iter > 0 ? o.max_iter : 1)
                                     : (o.check_every > 0 ? o.check_every : 8);
+    // one reduction per iteration: vector update, w = A z with w.z, finalize
     auto iterate = [&](hipStream_t st_s, int32_t count) {
         for (int32_t it = 0; it < count; ++it) {
-            const int nb_s = launch_cg_spmm<R>(m, ra, M, rb, K, mask, k, p, q, part, st_s);
-            launch_fin<FIN_ALPHA>(part, nb_s, k, st, prm, nullptr, st_s);
-            DGO_LAUNCH("cg_update", st_s,
-                       k_cg_update<R><<<nb_v, T, 0, st_s>>>((int32_t)nV, k, KP, r, q, invD, st, part));
-            launch_fin<FIN_BETA>(part, (int)nb_v, k, st, prm, nullptr, st_s);
-            DGO_LAUNCH("cg_pupdate", st_s,
-                       k_cg_pupdate<R><<<nb_p, T, 0, st_s>>>((int32_t)nV, k, KP, u, p, r, invD, st));
+            DGO_LAUNCH("cg_vupdate", st_s,
+                       k_cg_vupdate<R><<<nb_v, TR, 0, st_s>>>((int32_t)nV, k, KP, u, r, p, sv, w, invD,
+                                                             st, part));
+            const int nbs = launch_sdot<R>(m, v, invD, k, r, w, part2, st_s);
+            launch_fin<FIN_SR_ITER>(part, (int)nb_v, part2, nbs, k, st, prm, nullptr, st_s);
         }
     };
     // Opt-in (DGO_PCG_GRAPH=1): replay full chunks from a graph when the same
@@ -464,7 +524,7 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     const bool graphs = !trace_active() && getenv("DGO_PCG_GRAPH") && atoi(getenv("DGO_PCG_GRAPH")) > 0;
     uint64_t key[24] = {(uint64_t)(uintptr_t)M, (uint64_t)(uintptr_t)K, (uint64_t)(uintptr_t)mask,
                         (uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)ws, (uint64_t)total,
-                        (uint64_t)k, (uint64_t)every, (uint64_t)sizeof(R), nb_v, nb_p,
+                        (uint64_t)k, (uint64_t)every, (uint64_t)sizeof(R), nb_v, (uint64_t)nb_s,
                         0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1};
     memcpy(&key[11], &alpha, 8);
     memcpy(&key[12], &beta, 8);
@@ -515,9 +575,9 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
         if (!any) break;
     }
     DGO_LAUNCH("cg_trueres", s,
-               k_cg_trueres<R><<<nb_v, T, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta, K,
+               k_cg_trueres<R><<<nb_v, TR, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta, K,
                                                   mask, k, KP, beff, u, part));
-    launch_fin<FIN_OUT>(part, (int)nb_v, k, st, prm, tr, s);
+    launch_fin<FIN_OUT>(part, (int)nb_v, nullptr, 0, k, st, prm, tr, s);
     DGO_HIP(hipGetLastError());
     double htr[kMaxK];
     DGO_HIP(hipMemcpyAsync(hst, st, sizeof(CgCol) * k, hipMemcpyDeviceToHost, s));
@@ -558,6 +618,8 @@ extern "C" dgo_status dgo_spmv(const dgo_mesh *m, dgo_dtype dtype, int32_t batch
     if (batch < 1 || batch > 65535) return fail(DGO_ERR_INVALID_ARG, "dgo_spmv: bad batch");
     if (d_x == d_y) return fail(DGO_ERR_INVALID_ARG, "dgo_spmv: x and y alias");
     if (dtype != DGO_F32 && dtype != DGO_F64) return fail(DGO_ERR_INVALID_ARG, "dgo_spmv: bad dtype");
+    if (!m->rdesc || !m->rlen)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_spmv: mesh was built without SpMV row descriptors");
     hipStream_t s = (hipStream_t)stream;
     if (dtype == DGO_F64)
         launch_spmm<double>(m, batch, alpha, (const double *)d_Mdiag, beta, (const double *)d_Kvals, k,
@@ -579,6 +641,8 @@ extern "C" dgo_status dgo_pcg(const dgo_mesh *m, dgo_dtype dtype, double alpha, 
     if (k < 1 || k > kMaxK) return fail(DGO_ERR_INVALID_ARG, "dgo_pcg: k must be in [1, 64]");
     if (d_mask && !d_g) return fail(DGO_ERR_INVALID_ARG, "dgo_pcg: mask given without g");
     if (dtype != DGO_F32 && dtype != DGO_F64) return fail(DGO_ERR_INVALID_ARG, "dgo_pcg: bad dtype");
+    if (!m->rdesc || !m->rlen)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_pcg: mesh was built without SpMV row descriptors");
     dgo_cg_opts o;
     if (opts) {
         o = *opts;

@@ -14,6 +14,7 @@
 
 #include <climits>
 #include <new>
+#include <vector>
 
 namespace dgo {
 
@@ -507,6 +508,68 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
     return DGO_OK;
 }
 
+namespace {
+__global__ void k_row_desc(const int32_t *order, const int32_t *rowptr, int32_t nV, int2 *rdesc,
+                           uint8_t *rlen) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nV) return;
+    const int32_t i = order ? order[r] : (int32_t)r;
+    const int32_t b = rowptr[i];
+    rdesc[r] = make_int2(i, b);
+    rlen[r] = (uint8_t)(rowptr[i + 1] - b);  // at most 255 (checked by build)
+}
+}  // namespace
+
+// Row order for the SpMV kernels. For large meshes: breadth-first search over
+// the CSR pattern from the lowest-numbered unvisited vertex of each
+// component, neighbours in ascending column order (a deterministic function
+// of the pattern). Each XCD takes a contiguous range of positions, i.e. a band
+// of BFS levels, so the x rows its rows gather are mostly those of its own
+// band and stay in its L2; in the natural order of a subdivided mesh a
+// vertex's neighbours are spread over the whole index range. Small meshes keep
+// the natural order (their x fits every L2).
+static dgo_status build_row_desc(dgo_mesh *m, hipStream_t s, bool bfs) {
+    const int32_t nV = m->nV;
+    m->rdesc = (int2 *)m->alloc.get(sizeof(int2) * (size_t)nV, s);
+    m->rlen = (uint8_t *)m->alloc.get((size_t)nV, s);
+    if (!m->rdesc || !m->rlen) return fail(DGO_ERR_NOMEM, "mesh: row descriptor allocation failed");
+    if (!bfs || nV < kRowOrderMinRows) {
+        k_row_desc<<<grid_for(nV, T), T, 0, s>>>(nullptr, m->rowptr, nV, m->rdesc, m->rlen);
+        DGO_HIP(hipGetLastError());
+        return DGO_OK;
+    }
+    std::vector<int32_t> rp((size_t)nV + 1), cl((size_t)m->nnz), order;
+    DGO_HIP(hipMemcpyAsync(rp.data(), m->rowptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost, s));
+    DGO_HIP(hipMemcpyAsync(cl.data(), m->col, sizeof(int32_t) * cl.size(), hipMemcpyDeviceToHost, s));
+    DGO_HIP(hipStreamSynchronize(s));
+    order.reserve((size_t)nV);
+    std::vector<uint8_t> seen((size_t)nV, 0);
+    for (int32_t root = 0; root < nV; ++root) {
+        if (seen[root]) continue;
+        seen[root] = 1;
+        size_t head = order.size();
+        order.push_back(root);
+        while (head < order.size()) {
+            const int32_t v = order[head++];
+            for (int32_t t = rp[v]; t < rp[v + 1]; ++t) {
+                const int32_t j = cl[t];
+                if (!seen[j]) {
+                    seen[j] = 1;
+                    order.push_back(j);
+                }
+            }
+        }
+    }
+    Tmp tmp(m->alloc, s);
+    int32_t *d_order = tmp.get<int32_t>((size_t)nV);
+    if (!d_order) return fail(DGO_ERR_NOMEM, "mesh: row order allocation failed");
+    DGO_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * (size_t)nV, hipMemcpyHostToDevice, s));
+    k_row_desc<<<grid_for(nV, T), T, 0, s>>>(d_order, m->rowptr, nV, m->rdesc, m->rlen);
+    DGO_HIP(hipGetLastError());
+    DGO_HIP(hipStreamSynchronize(s));  // `order` is freed on return
+    return DGO_OK;
+}
+
 static void release(dgo_mesh *m, hipStream_t s) {
     mesh_drop_graph(m);
     if (m->graph_ev[0]) (void)hipEventDestroy(m->graph_ev[0]);
@@ -515,7 +578,7 @@ static void release(dgo_mesh *m, hipStream_t s) {
     m->graph_ev[0] = m->graph_ev[1] = nullptr;
     m->graph_stream = nullptr;
     void *ptrs[] = {m->elem, m->EV, m->elem_edge, m->elem_sign, m->rowptr, m->col,
-                    m->diag, m->vtptr, m->inc, m->bmask, m->ws};
+                    m->diag, m->vtptr, m->inc, m->bmask, m->rdesc, m->rlen, m->ws};
     for (void *p : ptrs) m->alloc.put(p, s);
 }
 
@@ -523,9 +586,9 @@ static void release(dgo_mesh *m, hipStream_t s) {
 
 using namespace dgo;
 
-extern "C" dgo_status dgo_mesh_create(int32_t dim, int32_t nV, int64_t n_elem,
-                                      const int32_t *d_elem, const dgo_allocator *alloc,
-                                      dgo_stream stream, dgo_mesh **out) {
+dgo_status dgo::mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_t *d_elem,
+                            const dgo_allocator *alloc, hipStream_t s, RowsMode rows,
+                            dgo_mesh **out) {
     clear_error();
     if (!out) return fail(DGO_ERR_INVALID_ARG, "dgo_mesh_create: out is NULL");
     *out = nullptr;
@@ -536,7 +599,6 @@ extern "C" dgo_status dgo_mesh_create(int32_t dim, int32_t nV, int64_t n_elem,
         return fail(DGO_ERR_UNSUPPORTED, "dgo_mesh_create: too many elements for int32 occurrence ids");
     if (alloc && (!alloc->alloc || !alloc->free))
         return fail(DGO_ERR_INVALID_ARG, "dgo_mesh_create: allocator callbacks missing");
-    hipStream_t s = (hipStream_t)stream;
     dgo_mesh *m = new (std::nothrow) dgo_mesh();
     if (!m) return fail(DGO_ERR_NOMEM, "dgo_mesh_create: host allocation failed");
     m->dim = dim;
@@ -551,6 +613,7 @@ extern "C" dgo_status dgo_mesh_create(int32_t dim, int32_t nV, int64_t n_elem,
     m->home = s;
     (void)hipGetDevice(&m->device);
     dgo_status st = build(m, d_elem, s);
+    if (st == DGO_OK && rows != ROWS_NONE) st = build_row_desc(m, s, rows == ROWS_AUTO);
     if (st != DGO_OK) {
         std::string msg = dgo_last_error();
         (void)hipStreamSynchronize(s);
@@ -562,6 +625,12 @@ extern "C" dgo_status dgo_mesh_create(int32_t dim, int32_t nV, int64_t n_elem,
     }
     *out = m;
     return DGO_OK;
+}
+
+extern "C" dgo_status dgo_mesh_create(int32_t dim, int32_t nV, int64_t n_elem,
+                                      const int32_t *d_elem, const dgo_allocator *alloc,
+                                      dgo_stream stream, dgo_mesh **out) {
+    return mesh_create(dim, nV, n_elem, d_elem, alloc, (hipStream_t)stream, ROWS_AUTO, out);
 }
 
 extern "C" void dgo_mesh_destroy(dgo_mesh *m) {

@@ -155,6 +155,13 @@ def test_spmv_parity(name, k, dtype):
     assert np.all(np.abs(y - yo) <= RTOL[dtype] * sc)
 
 
+@pytest.mark.parametrize("k", [1, 8])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmv_parity_breadth_first_rows(k, dtype):
+    """Meshes of 16384 vertices or more are swept in breadth-first row order."""
+    test_spmv_parity("ico7", k, dtype)
+
+
 def test_spmv_batch():
     X, E, m = _mesh("ico3")
     Xb = torch.from_numpy(np.stack([X, 1.1 * X])).to(DEV)
@@ -219,10 +226,11 @@ def test_pcg_cfg2_f32_accuracy():
     assert err <= 1e-5, (err, rep)
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_pcg_dirichlet_cube(dtype):
-    print(f"[pcg-dirichlet] cube17 {dtype}", flush=True)
-    X, T = meshgen.cube_tets(17, 0.15, 0)
+@pytest.mark.parametrize("n,dtype", [(17, "f64"), (17, "f32"), (26, "f64")])
+def test_pcg_dirichlet_cube(n, dtype):
+    """n = 26 (17,576 vertices) runs the masked SpMV in breadth-first row order."""
+    print(f"[pcg-dirichlet] cube{n} {dtype}", flush=True)
+    X, T = meshgen.cube_tets(n, 0.15, 0)
     m = dgo.Mesh(torch.from_numpy(T).to(DEV), X.shape[0])
     td = torch.float64 if dtype == "f64" else torch.float32
     K, M = dgo.assemble(m, torch.from_numpy(X).to(DEV, td))
