@@ -102,6 +102,14 @@ struct dgo_mesh {
     // CSR entries start at rdesc[r].y, rlen[r] of them
     int2 *rdesc = nullptr;         // nV
     uint8_t *rlen = nullptr;       // nV
+    int32_t *order = nullptr;      // nV, row at each position (NULL: natural order)
+    // padded-row copy of the pattern in that order, for meshes whose rows
+    // have at most kEllMaxWidth entries (ell_w = 0: none): position p's
+    // entries are slots [p * ell_w, (p + 1) * ell_w), holding column
+    // positions (padding: p itself) and the CSR slot of each entry (-1)
+    int32_t ell_w = 0;
+    int32_t *ell_col = nullptr;    // nV x ell_w
+    int32_t *ell_src = nullptr;    // nV x ell_w
 
     // row blocks for the row-centric kernels
     int32_t rpb = 0;            // rows per workgroup
@@ -134,17 +142,21 @@ bool trace_active();
 // vertices, natural below).
 enum RowsMode { ROWS_NONE = 0, ROWS_NATURAL = 1, ROWS_AUTO = 2 };
 constexpr int32_t kRowOrderMinRows = 16384;
+constexpr int32_t kEllMaxWidth = 16;
 dgo_status mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_t *d_elem,
                        const dgo_allocator *alloc, hipStream_t s, RowsMode rows,
                        dgo_mesh **out);
 
 // Workspace of one PCG solve (byte offsets): vectors r, p, s, w, the
-// effective right-hand side, D^-1, the scaled operator values, two arrays of
-// workgroup partial sums, the per-column state and the true residuals.
+// effective right-hand side and x in row order, D^-1 in natural and in row
+// order, the scaled operator values, two arrays of workgroup partial sums,
+// the per-column state and the true residuals.
 struct PcgLayout {
-    size_t off_r, off_p, off_s, off_w, off_b, off_d, off_v, off_pt, off_pt2, off_st, off_tr, total;
+    size_t off_r, off_p, off_s, off_w, off_b, off_x, off_d, off_dp, off_v, off_pt, off_pt2, off_st,
+        off_tr, total;
 };
-PcgLayout pcg_layout(int64_t nV, int64_t nnz, int k, size_t elem);
+// nvals: operator values stored per solve (nnz, or nV x ell_w)
+PcgLayout pcg_layout(int64_t nV, int64_t nvals, int k, size_t elem);
 
 // Release the cached graph of a mesh (if any).
 void mesh_drop_graph(dgo_mesh *m);

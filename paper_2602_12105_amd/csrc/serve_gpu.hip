@@ -252,9 +252,11 @@ int64_t footprint_of(int32_t nV, int64_t nF, int32_t k, bool per_mesh_path) {
     if (per_mesh_path) {
         // the per-mesh PCG workspace (grown once, with headroom) and the
         // assembly counter
-        const int64_t ws = (int64_t)pcg_layout(nV, nnz, k, sizeof(float)).total;
+        const int64_t nvals = std::max<int64_t>(nnz, (int64_t)kEllMaxWidth * nV);
+        const int64_t ws = (int64_t)pcg_layout(nV, nvals, k, sizeof(float)).total;
         b += rnd(ws + ws / 4) + rnd(320);
-        b += rnd(8 * (int64_t)nV) + rnd(nV);  // SpMV row descriptors
+        // SpMV row descriptors and the padded-row pattern
+        b += rnd(8 * (int64_t)nV) + rnd(nV) + 2 * rnd(4 * (int64_t)kEllMaxWidth * nV);
     }
     return b + 8192;
 }

@@ -117,11 +117,15 @@ k_cg_spmm_dot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
 }
 
 // r = beff - q, p = s = 0; partial sums of r.z, r.r, beff.beff (z = D^-1 r).
+// With xp != NULL the solve runs in row order: position p takes row
+// order[p] (identity if order is NULL) of beff, q and x0 (copied to xp), and
+// dvec is D^-1 in row order.
 template <typename R>
 __global__ void __launch_bounds__(TR)
-k_cg_init(int32_t nV, int k, int KP, const R *__restrict__ beff, const R *__restrict__ q,
-          const R *__restrict__ invD, R *__restrict__ r, R *__restrict__ p, R *__restrict__ sv,
-          double *__restrict__ part) {
+k_cg_init(int32_t nV, int k, int KP, const int32_t *__restrict__ order,
+          const R *__restrict__ beff, const R *__restrict__ q, const R *__restrict__ x0,
+          R *__restrict__ xp, const R *__restrict__ dvec, R *__restrict__ r, R *__restrict__ p,
+          R *__restrict__ sv, double *__restrict__ part) {
     __shared__ double s_part[3 * kMaxK];
     __shared__ double s_red[red_scratch(TR, 3)];
     const VLane L = vlane(k, KP);
@@ -132,9 +136,11 @@ k_cg_init(int32_t nV, int k, int KP, const R *__restrict__ beff, const R *__rest
         const int64_t i = tile * L.gpb + L.grp;
         if (i >= nV || !L.act) continue;
         const int64_t e = i * k + L.c;
-        const R b = beff[e];
-        const R rv = b - q[e];
-        const R zv = invD[i] * rv;
+        const int64_t en = (order ? (int64_t)order[i] : i) * k + L.c;
+        const R b = beff[en];
+        const R rv = b - q[en];
+        const R zv = dvec[i] * rv;
+        if (xp) xp[e] = x0[en];
         r[e] = rv;
         p[e] = R(0);
         sv[e] = R(0);
@@ -144,6 +150,41 @@ k_cg_init(int32_t nV, int k, int KP, const R *__restrict__ beff, const R *__rest
     }
     column_partials(d, 3, k, KP, L.act, s_red, s_part);
     store_partials(s_part, 3 * k, part);
+}
+
+// x[order[p]] = xp[p] (row-order solution back to natural order).
+template <typename R>
+__global__ void k_cg_unorder(int64_t n, int k, const int32_t *__restrict__ order,
+                             const R *__restrict__ xp, R *__restrict__ x) {
+    const int64_t e = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (e >= n) return;
+    const int64_t p = e / k;
+    x[(order ? (int64_t)order[p] : p) * k + (e - p * k)] = xp[e];
+}
+
+// Padded-row values: slot q = p * W + t holds v = A_ij d_j for the entry of
+// CSR slot ell_src[q] (row i = order[p], column j), 0 for padding and on
+// masked rows; dp[p] = d_i (D^-1 in row order).
+template <typename R>
+__global__ void k_cg_values_ell(const int32_t *__restrict__ order, const int32_t *__restrict__ src,
+                                const int32_t *__restrict__ col, int32_t nV, int32_t W, R alpha,
+                                const R *__restrict__ M, R beta, const R *__restrict__ K,
+                                const uint8_t *__restrict__ mask, const R *__restrict__ invD,
+                                R *__restrict__ v, R *__restrict__ dp) {
+    const int64_t q = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (q >= (int64_t)nV * W) return;
+    const int64_t p = q / W;
+    const int32_t i = order ? order[p] : (int32_t)p;
+    const int32_t t = src[q];
+    R val = R(0);
+    if (t >= 0 && !(mask && mask[i])) {
+        const int32_t j = col[t];
+        R a = beta * K[t];
+        if (j == i) a += alpha * M[i];
+        val = a * invD[j];
+    }
+    v[q] = val;
+    if (q - p * W == 0) dp[p] = invD[i];
 }
 
 // The operator's values scaled by the preconditioner, v_ij = A_ij d_j with
@@ -169,11 +210,14 @@ __global__ void k_cg_values(const int32_t *__restrict__ rowptr, const int32_t *_
 
 // w = A_II z with z = D^-1 r, as w_i = sum_j v_ij r_j, fused with per-column
 // partial sums of w.z. Rows in the mesh's row order (as k_spmm).
-template <typename R, int KP>
+// ELL: the padded rows in row order (vectors in row order, i = position,
+// dvec = D^-1 in row order); otherwise CSR rows through the row descriptors
+// (vectors in natural order).
+template <typename R, int KP, bool ELL>
 __global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
-k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
+k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int32_t W,
           const int32_t *__restrict__ col, int32_t nV, const R *__restrict__ v,
-          const R *__restrict__ invD, int k, const R *__restrict__ r, R *__restrict__ w,
+          const R *__restrict__ dvec, int k, const R *__restrict__ r, R *__restrict__ w,
           double *__restrict__ part) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = TR / G;
@@ -188,12 +232,20 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t pos = tile * GPB + grp;
         if (pos >= nV) continue;  // uniform over the lane group
-        const int2 d = rdesc[pos];
-        const int32_t i = d.x;
-        const int32_t len = rlen[pos];
-        const R di = invD[i];
+        int32_t i, rb, len;
+        if (ELL) {
+            i = (int32_t)pos;
+            rb = i * W;
+            len = W;
+        } else {
+            const int2 d = rdesc[pos];
+            i = d.x;
+            rb = d.y;
+            len = rlen[pos];
+        }
+        const R di = dvec[i];
         R ri = 0;
-        const R acc = row_apply<R, G, KP, false>(col, v, R(1), R(0), nullptr, r, i, d.y, len, k,
+        const R acc = row_apply<R, G, KP, false>(col, v, R(1), R(0), nullptr, r, i, rb, len, k,
                                                  lane, gbase, &ri);
         if (out_lane) {
             const int64_t e = (int64_t)i * k + lane;
@@ -408,33 +460,38 @@ void launch_fin(const double *part, int nblk, const double *part2, int nblk2, in
 }
 
 template <typename R, int KP>
-int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *invD, int k, const R *r, R *w,
+int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R *r, R *w,
                    double *part, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
     const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), kMaxRedBlocks);
-    DGO_LAUNCH("cg_sdot", s,
-               k_cg_sdot<R, KP><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV, v, invD, k, r,
-                                                 w, part));
+    if (m->ell_w)
+        DGO_LAUNCH("cg_sdot", s,
+                   k_cg_sdot<R, KP, true><<<nb, TR, 0, s>>>(nullptr, nullptr, m->ell_w, m->ell_col,
+                                                            m->nV, v, dvec, k, r, w, part));
+    else
+        DGO_LAUNCH("cg_sdot", s,
+                   k_cg_sdot<R, KP, false><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, 0, m->col, m->nV, v,
+                                                             dvec, k, r, w, part));
     return (int)nb;
 }
 
 template <typename R>
-int launch_sdot(const dgo_mesh *m, const R *v, const R *invD, int k, const R *r, R *w,
+int launch_sdot(const dgo_mesh *m, const R *v, const R *dvec, int k, const R *r, R *w,
                 double *part, hipStream_t s) {
     switch (pow2ceil(k)) {
-        case 1: return launch_sdot_kp<R, 1>(m, v, invD, k, r, w, part, s);
-        case 2: return launch_sdot_kp<R, 2>(m, v, invD, k, r, w, part, s);
-        case 4: return launch_sdot_kp<R, 4>(m, v, invD, k, r, w, part, s);
-        case 8: return launch_sdot_kp<R, 8>(m, v, invD, k, r, w, part, s);
-        case 16: return launch_sdot_kp<R, 16>(m, v, invD, k, r, w, part, s);
-        case 32: return launch_sdot_kp<R, 32>(m, v, invD, k, r, w, part, s);
-        default: return launch_sdot_kp<R, 64>(m, v, invD, k, r, w, part, s);
+        case 1: return launch_sdot_kp<R, 1>(m, v, dvec, k, r, w, part, s);
+        case 2: return launch_sdot_kp<R, 2>(m, v, dvec, k, r, w, part, s);
+        case 4: return launch_sdot_kp<R, 4>(m, v, dvec, k, r, w, part, s);
+        case 8: return launch_sdot_kp<R, 8>(m, v, dvec, k, r, w, part, s);
+        case 16: return launch_sdot_kp<R, 16>(m, v, dvec, k, r, w, part, s);
+        case 32: return launch_sdot_kp<R, 32>(m, v, dvec, k, r, w, part, s);
+        default: return launch_sdot_kp<R, 64>(m, v, dvec, k, r, w, part, s);
     }
 }
 
 }  // namespace
 
-PcgLayout pcg_layout(int64_t nV, int64_t nnz, int k, size_t elem) {
+PcgLayout pcg_layout(int64_t nV, int64_t nvals, int k, size_t elem) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t vec = al(elem * (size_t)nV * (size_t)k);
     PcgLayout L;
@@ -443,9 +500,11 @@ PcgLayout pcg_layout(int64_t nV, int64_t nnz, int k, size_t elem) {
     L.off_s = 2 * vec;
     L.off_w = 3 * vec;
     L.off_b = 4 * vec;
-    L.off_d = 5 * vec;
-    L.off_v = L.off_d + al(elem * (size_t)nV);
-    L.off_pt = L.off_v + al(elem * (size_t)nnz);
+    L.off_x = 5 * vec;
+    L.off_d = 6 * vec;
+    L.off_dp = L.off_d + al(elem * (size_t)nV);
+    L.off_v = L.off_dp + al(elem * (size_t)nV);
+    L.off_pt = L.off_v + al(elem * (size_t)nvals);
     L.off_pt2 = L.off_pt + al(sizeof(double) * kern::kMaxRedBlocks * 3 * kern::kMaxK);
     L.off_st = L.off_pt2 + al(sizeof(double) * kern::kMaxRedBlocks * kern::kMaxK);
     L.off_tr = L.off_st + al(sizeof(kern::CgCol) * kern::kMaxK);
@@ -461,21 +520,25 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
                    dgo_cg_report *rep, hipStream_t s) {
     const int64_t nV = m->nV, n = nV * k;
     const int KP = pow2ceil(k);
-    const PcgLayout L = pcg_layout(nV, m->nnz, k, sizeof(R));
-    const size_t off_r = L.off_r, off_p = L.off_p, off_s = L.off_s, off_w = L.off_w;
-    const size_t off_b = L.off_b, off_d = L.off_d, off_v = L.off_v, off_pt = L.off_pt;
-    const size_t off_pt2 = L.off_pt2, off_st = L.off_st, off_tr = L.off_tr, total = L.total;
+    // With a padded-row layout the iteration runs in the mesh's row order
+    // (vectors permuted once in and once out); otherwise in natural order.
+    const bool ell = m->ell_w > 0;
+    const int64_t nvals = ell ? nV * m->ell_w : m->nnz;
+    const PcgLayout L = pcg_layout(nV, nvals, k, sizeof(R));
     void *wsv;
-    DGO_TRY(mesh_workspace(const_cast<dgo_mesh *>(m), total, s, &wsv));
+    DGO_TRY(mesh_workspace(const_cast<dgo_mesh *>(m), L.total, s, &wsv));
     char *ws = (char *)wsv;
-    R *r = (R *)(ws + off_r), *p = (R *)(ws + off_p), *sv = (R *)(ws + off_s);
-    R *w = (R *)(ws + off_w);
-    R *beff = mask ? (R *)(ws + off_b) : const_cast<R *>(b);
-    R *invD = (R *)(ws + off_d);
-    R *v = (R *)(ws + off_v);
-    double *part = (double *)(ws + off_pt), *part2 = (double *)(ws + off_pt2);
-    CgCol *st = (CgCol *)(ws + off_st);
-    double *tr = (double *)(ws + off_tr);
+    R *r = (R *)(ws + L.off_r), *p = (R *)(ws + L.off_p), *sv = (R *)(ws + L.off_s);
+    R *w = (R *)(ws + L.off_w);
+    R *beff = mask ? (R *)(ws + L.off_b) : const_cast<R *>(b);
+    R *x = ell ? (R *)(ws + L.off_x) : u;             // iterate in the loop's order
+    R *invD = (R *)(ws + L.off_d);                     // natural order
+    R *dvec = ell ? (R *)(ws + L.off_dp) : invD;       // the loop's order
+    R *v = (R *)(ws + L.off_v);
+    double *part = (double *)(ws + L.off_pt), *part2 = (double *)(ws + L.off_pt2);
+    CgCol *st = (CgCol *)(ws + L.off_st);
+    double *tr = (double *)(ws + L.off_tr);
+    const size_t total = L.total;
 
     CgParams prm;
     prm.rtol = o.rtol;
@@ -490,9 +553,15 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     DGO_LAUNCH("cg_invdiag", s,
                k_cg_invdiag<R><<<grid_for(nV, T), T, 0, s>>>((int32_t)nV, ra, M, rb, K, m->diag, mask,
                                                              invD));
-    DGO_LAUNCH("cg_values", s,
-               k_cg_values<R><<<grid_for(nV, T), T, 0, s>>>(m->rowptr, m->col, (int32_t)nV, ra, M, rb,
-                                                            K, mask, invD, v));
+    if (ell)
+        DGO_LAUNCH("cg_values", s,
+                   k_cg_values_ell<R><<<grid_for(nvals, T), T, 0, s>>>(
+                       m->order, m->ell_src, m->col, (int32_t)nV, m->ell_w, ra, M, rb, K, mask, invD,
+                       v, dvec));
+    else
+        DGO_LAUNCH("cg_values", s,
+                   k_cg_values<R><<<grid_for(nV, T), T, 0, s>>>(m->rowptr, m->col, (int32_t)nV, ra,
+                                                                M, rb, K, mask, invD, v));
     if (mask)
         DGO_LAUNCH("cg_lift", s,
                    k_cg_lift<R><<<grid_for(n, T), T, 0, s>>>(m->rowptr, m->col, (int32_t)nV, ra, M, rb,
@@ -500,8 +569,9 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     // r0 = beff - A_II x0, p = s = 0, w0 = A D^-1 r0; alpha_0 = (r.z) / (w.z)
     launch_cg_spmm<R>(m, ra, M, rb, K, mask, k, u, w, nullptr, s);
     DGO_LAUNCH("cg_init", s,
-               k_cg_init<R><<<nb_v, TR, 0, s>>>((int32_t)nV, k, KP, beff, w, invD, r, p, sv, part));
-    int nb_s = launch_sdot<R>(m, v, invD, k, r, w, part2, s);
+               k_cg_init<R><<<nb_v, TR, 0, s>>>((int32_t)nV, k, KP, ell ? m->order : nullptr, beff,
+                                                w, u, ell ? x : nullptr, dvec, r, p, sv, part));
+    int nb_s = launch_sdot<R>(m, v, dvec, k, r, w, part2, s);
     launch_fin<FIN_SR_INIT>(part, (int)nb_v, part2, nb_s, k, st, prm, nullptr, s);
     DGO_HIP(hipGetLastError());
 
@@ -511,9 +581,9 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     auto iterate = [&](hipStream_t st_s, int32_t count) {
         for (int32_t it = 0; it < count; ++it) {
             DGO_LAUNCH("cg_vupdate", st_s,
-                       k_cg_vupdate<R><<<nb_v, TR, 0, st_s>>>((int32_t)nV, k, KP, u, r, p, sv, w, invD,
+                       k_cg_vupdate<R><<<nb_v, TR, 0, st_s>>>((int32_t)nV, k, KP, x, r, p, sv, w, dvec,
                                                              st, part));
-            const int nbs = launch_sdot<R>(m, v, invD, k, r, w, part2, st_s);
+            const int nbs = launch_sdot<R>(m, v, dvec, k, r, w, part2, st_s);
             launch_fin<FIN_SR_ITER>(part, (int)nb_v, part2, nbs, k, st, prm, nullptr, st_s);
         }
     };
@@ -574,6 +644,9 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
         for (int c = 0; c < k; ++c) any = any || hst[c].active;
         if (!any) break;
     }
+    if (ell)
+        DGO_LAUNCH("cg_unorder", s,
+                   k_cg_unorder<R><<<grid_for(n, T), T, 0, s>>>(n, k, m->order, x, u));
     DGO_LAUNCH("cg_trueres", s,
                k_cg_trueres<R><<<nb_v, TR, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta, K,
                                                   mask, k, KP, beff, u, part));

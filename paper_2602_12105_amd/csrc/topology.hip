@@ -518,6 +518,31 @@ __global__ void k_row_desc(const int32_t *order, const int32_t *rowptr, int32_t 
     rdesc[r] = make_int2(i, b);
     rlen[r] = (uint8_t)(rowptr[i + 1] - b);  // at most 255 (checked by build)
 }
+
+__global__ void k_inverse_perm(const int32_t *order, int32_t nV, int32_t *pos) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nV) pos[order[p]] = (int32_t)p;
+}
+
+// Slot t of position p: the row's t-th entry (column position, CSR slot), or
+// padding (p, -1) past the row's end. Rows have at most W entries.
+__global__ void k_build_ell(const int32_t *order, const int32_t *pos, const int32_t *rowptr,
+                            const int32_t *col, int32_t nV, int32_t W, int32_t *ell_col,
+                            int32_t *ell_src) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)nV * W) return;
+    const int32_t p = (int32_t)(q / W), t = (int32_t)(q % W);
+    const int32_t i = order ? order[p] : p;
+    const int32_t b = rowptr[i], len = rowptr[i + 1] - b;
+    if (t < len) {
+        const int32_t j = col[b + t];
+        ell_col[q] = pos ? pos[j] : j;
+        ell_src[q] = b + t;
+    } else {
+        ell_col[q] = p;
+        ell_src[q] = -1;
+    }
+}
 }  // namespace
 
 // Row order for the SpMV kernels. For large meshes: breadth-first search over
@@ -533,39 +558,55 @@ static dgo_status build_row_desc(dgo_mesh *m, hipStream_t s, bool bfs) {
     m->rdesc = (int2 *)m->alloc.get(sizeof(int2) * (size_t)nV, s);
     m->rlen = (uint8_t *)m->alloc.get((size_t)nV, s);
     if (!m->rdesc || !m->rlen) return fail(DGO_ERR_NOMEM, "mesh: row descriptor allocation failed");
-    if (!bfs || nV < kRowOrderMinRows) {
-        k_row_desc<<<grid_for(nV, T), T, 0, s>>>(nullptr, m->rowptr, nV, m->rdesc, m->rlen);
-        DGO_HIP(hipGetLastError());
-        return DGO_OK;
-    }
-    std::vector<int32_t> rp((size_t)nV + 1), cl((size_t)m->nnz), order;
-    DGO_HIP(hipMemcpyAsync(rp.data(), m->rowptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost, s));
-    DGO_HIP(hipMemcpyAsync(cl.data(), m->col, sizeof(int32_t) * cl.size(), hipMemcpyDeviceToHost, s));
-    DGO_HIP(hipStreamSynchronize(s));
-    order.reserve((size_t)nV);
-    std::vector<uint8_t> seen((size_t)nV, 0);
-    for (int32_t root = 0; root < nV; ++root) {
-        if (seen[root]) continue;
-        seen[root] = 1;
-        size_t head = order.size();
-        order.push_back(root);
-        while (head < order.size()) {
-            const int32_t v = order[head++];
-            for (int32_t t = rp[v]; t < rp[v + 1]; ++t) {
-                const int32_t j = cl[t];
-                if (!seen[j]) {
-                    seen[j] = 1;
-                    order.push_back(j);
+    std::vector<int32_t> order;
+    if (bfs && nV >= kRowOrderMinRows) {
+        std::vector<int32_t> rp((size_t)nV + 1), cl((size_t)m->nnz);
+        DGO_HIP(hipMemcpyAsync(rp.data(), m->rowptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost, s));
+        DGO_HIP(hipMemcpyAsync(cl.data(), m->col, sizeof(int32_t) * cl.size(), hipMemcpyDeviceToHost, s));
+        DGO_HIP(hipStreamSynchronize(s));
+        order.reserve((size_t)nV);
+        std::vector<uint8_t> seen((size_t)nV, 0);
+        for (int32_t root = 0; root < nV; ++root) {
+            if (seen[root]) continue;
+            seen[root] = 1;
+            size_t head = order.size();
+            order.push_back(root);
+            while (head < order.size()) {
+                const int32_t v = order[head++];
+                for (int32_t t = rp[v]; t < rp[v + 1]; ++t) {
+                    const int32_t j = cl[t];
+                    if (!seen[j]) {
+                        seen[j] = 1;
+                        order.push_back(j);
+                    }
                 }
             }
         }
+        m->order = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)nV, s);
+        if (!m->order) return fail(DGO_ERR_NOMEM, "mesh: row order allocation failed");
+        DGO_HIP(hipMemcpyAsync(m->order, order.data(), sizeof(int32_t) * (size_t)nV,
+                               hipMemcpyHostToDevice, s));
     }
-    Tmp tmp(m->alloc, s);
-    int32_t *d_order = tmp.get<int32_t>((size_t)nV);
-    if (!d_order) return fail(DGO_ERR_NOMEM, "mesh: row order allocation failed");
-    DGO_HIP(hipMemcpyAsync(d_order, order.data(), sizeof(int32_t) * (size_t)nV, hipMemcpyHostToDevice, s));
-    k_row_desc<<<grid_for(nV, T), T, 0, s>>>(d_order, m->rowptr, nV, m->rdesc, m->rlen);
+    k_row_desc<<<grid_for(nV, T), T, 0, s>>>(m->order, m->rowptr, nV, m->rdesc, m->rlen);
     DGO_HIP(hipGetLastError());
+    if (m->max_row <= kEllMaxWidth && (int64_t)nV * kEllMaxWidth < INT32_MAX) {
+        const int32_t W = m->max_row <= 8 ? 8 : kEllMaxWidth;
+        const int64_t ns = (int64_t)nV * W;
+        m->ell_col = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)ns, s);
+        m->ell_src = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)ns, s);
+        if (!m->ell_col || !m->ell_src) return fail(DGO_ERR_NOMEM, "mesh: padded-row allocation failed");
+        Tmp tmp(m->alloc, s);
+        int32_t *pos = nullptr;
+        if (m->order) {
+            pos = tmp.get<int32_t>(nV);
+            if (!pos) return fail(DGO_ERR_NOMEM, "mesh: row position allocation failed");
+            k_inverse_perm<<<grid_for(nV, T), T, 0, s>>>(m->order, nV, pos);
+        }
+        k_build_ell<<<grid_for(ns, T), T, 0, s>>>(m->order, pos, m->rowptr, m->col, nV, W,
+                                                   m->ell_col, m->ell_src);
+        DGO_HIP(hipGetLastError());
+        m->ell_w = W;
+    }
     DGO_HIP(hipStreamSynchronize(s));  // `order` is freed on return
     return DGO_OK;
 }
@@ -578,7 +619,8 @@ static void release(dgo_mesh *m, hipStream_t s) {
     m->graph_ev[0] = m->graph_ev[1] = nullptr;
     m->graph_stream = nullptr;
     void *ptrs[] = {m->elem, m->EV, m->elem_edge, m->elem_sign, m->rowptr, m->col,
-                    m->diag, m->vtptr, m->inc, m->bmask, m->rdesc, m->rlen, m->ws};
+                    m->diag, m->vtptr, m->inc, m->bmask, m->rdesc, m->rlen, m->order,
+                    m->ell_col, m->ell_src, m->ws};
     for (void *p : ptrs) m->alloc.put(p, s);
 }
 

@@ -43,6 +43,28 @@ def spmv_scale(rowptr, col, alpha, M, beta, K, x):
     return out
 
 
+def _fan(n, seed):
+    """A disk fan: center 0 and a ring of n vertices (row 0 has n + 1 entries)."""
+    th = np.linspace(0, 2 * np.pi, n, endpoint=False)
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n + 1, 3))
+    X[1:, 0], X[1:, 1] = np.cos(th), np.sin(th)
+    X[1:, 2] = 0.05 * rng.standard_normal(n)
+    F = np.array([[0, 1 + i, 1 + (i + 1) % n] for i in range(n)], np.int32)
+    return X, F
+
+
+def _grid_with_fan(n, m, seed):
+    """grid2d(n) plus one vertex below the bottom row joined to its first m + 1
+    vertices by m triangles (a row of m + 2 entries in a mesh of n^2 + 1
+    vertices)."""
+    X, F = meshgen.grid2d(n, 0.2, seed)
+    c = X.shape[0]
+    Xc = np.array([[0.5 * m / (n - 1), -0.3, 0.0]])
+    Ff = np.array([[c, i + 1, i] for i in range(m)], np.int32)
+    return np.vstack([X, Xc]), np.vstack([F, Ff]).astype(np.int32)
+
+
 MESHES = {
     "tri1": lambda: (np.array([[0.0, 0, 0], [1, 0, 0], [0.2, 0.9, 0]]), np.array([[0, 1, 2]], np.int32)),
     "tet1": lambda: (np.array([[0.0, 0, 0], [1, 0, 0], [0.1, 1, 0], [0.2, 0.3, 1]]),
@@ -59,4 +81,6 @@ MESHES = {
     "cube3": lambda: meshgen.cube_tets(3, 0.15, 0),
     "cube9": lambda: meshgen.cube_tets(9, 0.15, 0),
     "cube64": lambda: meshgen.cube_tets(64, 0.15, 0),
+    "fan40": lambda: _fan(40, 2),
+    "grid130fan": lambda: _grid_with_fan(130, 30, 3),
 }

@@ -162,6 +162,13 @@ def test_spmv_parity_breadth_first_rows(k, dtype):
     test_spmv_parity("ico7", k, dtype)
 
 
+@pytest.mark.parametrize("name", ["fan40", "grid130fan"])
+@pytest.mark.parametrize("k", [1, 8])
+def test_spmv_parity_long_rows(name, k):
+    """Rows of more than 16 entries (a fan centre)."""
+    test_spmv_parity(name, k, "f64")
+
+
 def test_spmv_batch():
     X, E, m = _mesh("ico3")
     Xb = torch.from_numpy(np.stack([X, 1.1 * X])).to(DEV)
@@ -194,6 +201,28 @@ def test_pcg_fixed_iterations_match_oracle(dtype):
     uo, its, rr = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3,
                              K.double().cpu().numpy(), b.double().cpu().numpy(), rtol=0.0,
                              max_iter=30)
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
+    assert err <= tol, err
+
+
+@pytest.mark.parametrize("name", ["fan40", "grid130fan"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pcg_long_rows_match_oracle(name, dtype):
+    """Meshes with a row of more than 16 entries iterate over CSR rows (in
+    natural order for fan40, in breadth-first order for grid130fan) instead
+    of the padded rows the other tests use."""
+    print(f"[pcg-long-rows] {name} {dtype}", flush=True)
+    X, E, m = _mesh(name)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    K, M = dgo.assemble(m, torch.from_numpy(X).to(DEV, td))
+    f = torch.from_numpy(meshgen.normal(5, X.shape[0] * 3).reshape(-1, 3)).to(DEV, td)
+    b = (M[:, None] * f).contiguous()
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=30, fixed_iters=True)
+    assert rep["iters"] == [30] * 3
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    uo, _, _ = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3, K.double().cpu().numpy(),
+                          b.double().cpu().numpy(), rtol=0.0, max_iter=30)
     tol = 1e-10 if dtype == "f64" else 1e-4
     err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
     assert err <= tol, err
