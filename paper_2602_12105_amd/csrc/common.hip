@@ -53,11 +53,6 @@ dgo_status mesh_workspace(dgo_mesh *m, size_t bytes, hipStream_t s, void **out) 
     return DGO_OK;
 }
 
-void mesh_drop_graph(dgo_mesh *m) {
-    if (m->graph) (void)hipGraphExecDestroy(m->graph);
-    m->graph = nullptr;
-    for (auto &k : m->graph_key) k = 0;
-}
 
 // ------------------------------------------------------------------ scan
 

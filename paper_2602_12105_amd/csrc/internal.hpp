@@ -121,18 +121,16 @@ struct dgo_mesh {
     void *ws = nullptr;
     size_t ws_bytes = 0;
 
-    // replayable graph of one chunk of solver iterations, valid for one exact
-    // set of launch arguments (key); replayed on a private stream joined to
-    // the caller's stream with events
-    hipGraphExec_t graph = nullptr;
-    uint64_t graph_key[24] = {};
-    hipStream_t graph_stream = nullptr;
-    hipEvent_t graph_ev[2] = {nullptr, nullptr};
+    // PCG progress polling: pinned host copies of the per-column state after
+    // each chunk of iterations and the events that mark them (two slots)
+    void *poll_host = nullptr;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
 };
 
 namespace dgo {
 
-// True while kernel tracing is enabled (graphs are not used then).
+// True while kernel tracing is enabled (the serving loop then launches
+// directly instead of replaying graphs).
 bool trace_active();
 
 // Build a mesh (dgo_mesh_create). `rows` selects the row descriptors of the
@@ -149,8 +147,9 @@ dgo_status mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_t *d
 
 // Workspace of one PCG solve (byte offsets): vectors r, p, s, w, the
 // effective right-hand side and x in row order, D^-1 in natural and in row
-// order, the scaled operator values, two arrays of workgroup partial sums,
-// the per-column state and the true residuals.
+// order, the scaled operator values, workgroup partial sums (two alternating
+// arrays of the vector update, one of the SpMV), the per-column state (two
+// alternating copies) and the true residuals.
 struct PcgLayout {
     size_t off_r, off_p, off_s, off_w, off_b, off_x, off_d, off_dp, off_v, off_pt, off_pt2, off_st,
         off_tr, total;
@@ -158,8 +157,6 @@ struct PcgLayout {
 // nvals: operator values stored per solve (nnz, or nV x ell_w)
 PcgLayout pcg_layout(int64_t nV, int64_t nvals, int k, size_t elem);
 
-// Release the cached graph of a mesh (if any).
-void mesh_drop_graph(dgo_mesh *m);
 
 // Grow the mesh workspace to at least `bytes`; contents are not preserved.
 dgo_status mesh_workspace(dgo_mesh *m, size_t bytes, hipStream_t s, void **out);
@@ -182,7 +179,7 @@ constexpr int kAssembleThreads = 256;
 
 inline int64_t assembly_lds_bytes(int dim, int s, int64_t rpb, int64_t span, int64_t ninc) {
     const int cw = dim == 2 ? 3 : 4;
-    return span * (4 * s + 4) + ninc * (cw * s + 4) + rpb * 3 * s + 2 * (rpb + 1) * 4 + 64;
+    return span * (s + 4) + ninc * (cw * s + 4) + rpb * 3 * s + 2 * (rpb + 1) * 4 + 64;
 }
 
 inline unsigned grid_for(int64_t n, int threads) {

@@ -124,19 +124,18 @@ __device__ __forceinline__ V3<R> sel2v(bool c, V3<R> a, V3<R> b) {
 // touching consecutive entries hit consecutive banks:
 //   acc  : R[span]          the block's CSR values (accumulated, then finished)
 //   cw   : R[CW][inc_max]   per-incidence contributions (phase A)
-//   xl   : R[3][span_max]   positions of the column vertex of each CSR entry
 //   xo   : R[3][rpb]        positions of the block's own vertices
 //   lcol : int32[span]      the block's column ids
 //   lrec : uint32[ninc]     the block's incidence records
 //   lrp  : int32[rpb + 1]   row offsets into the span
 //   lvt  : int32[rpb + 1]   row offsets into the incidence records
-// Every position an element needs is a column of the row it is accumulated
-// into, so phase A reads positions from LDS only: X is gathered once per CSR
-// entry of the block (coalesced in the CSR order) instead of three times per
-// incidence.
+// The other vertices' positions are gathered from X in phase A (they are
+// L2-resident: each is read by the few rows around it). Staging them in LDS
+// too was measured slower: the larger footprint allowed fewer resident
+// workgroups, and the kernel is bound by load latency, not by L2 traffic.
 template <typename R, int CW>
 struct BlockLds {
-    R *acc, *cw, *xl, *xo;
+    R *acc, *cw, *xo;
     int32_t *lcol, *lrp, *lvt;
     uint32_t *lrec;
     int32_t inc_max, span_max, rpb;
@@ -144,17 +143,13 @@ struct BlockLds {
         : inc_max(inc_max_), span_max(span_max_), rpb(rpb_) {
         acc = (R *)smem;
         cw = acc + span_max;
-        xl = cw + (size_t)inc_max * CW;
-        xo = xl + (size_t)span_max * 3;
+        xo = cw + (size_t)inc_max * CW;
         lcol = (int32_t *)(xo + (size_t)rpb * 3);
         lrec = (uint32_t *)(lcol + span_max);
         lrp = (int32_t *)(lrec + inc_max);
         lvt = lrp + rpb + 1;
     }
     __device__ R &c(int f, int32_t q) { return cw[(size_t)f * inc_max + q]; }
-    __device__ V3<R> pos(int32_t j) const {
-        return {xl[j], xl[span_max + j], xl[2 * span_max + j]};
-    }
     __device__ V3<R> own(int32_t r) const { return {xo[r], xo[rpb + r], xo[2 * rpb + r]}; }
 };
 
@@ -208,9 +203,6 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
         const int32_t c = col[s0 + j];
         L.lcol[j] = c;
         L.acc[j] = R(0);
-        L.xl[j] = X[3 * (int64_t)c];
-        L.xl[span_max + j] = X[3 * (int64_t)c + 1];
-        L.xl[2 * span_max + j] = X[3 * (int64_t)c + 2];
     }
     for (int32_t q = t; q < ninc; q += blockDim.x) L.lrec[q] = inc[q0 + q];
     __syncthreads();
@@ -224,22 +216,34 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
         const V3<R> xi = L.own(rr);
         if (DIM == 2) {
             const int32_t a = L.lcol[la], b = L.lcol[lb];
-            const V3<R> xa = L.pos(la), xb = L.pos(lb);
-            // edge (i, a) is opposite b and edge (i, b) is opposite a; the
-            // endpoints go in vertex-id order so both rows compute the same value
-            const R cb = i < a ? cot_at(xi, xa, xb) : cot_at(xa, xi, xb);
-            const R ca = i < b ? cot_at(xi, xb, xa) : cot_at(xb, xi, xa);
-            const V3<R> n = cross(sub(xa, xi), sub(xb, xi));
+            const V3<R> xa = ld3(X, a), xb = ld3(X, b);
+            // |n| = 2 area is shared by the triangle's three cotangents,
+            // cot = (e1 . e2) / |n|; n is formed from the vertices in id
+            // order and each dot product from the edge's endpoints in id
+            // order, so every row that needs a value computes the same bits
+            // (K stays exactly symmetric)
+            const bool ia = i < a, ib = i < b, ab = a < b;
+            const V3<R> v0 = ia ? (ib ? xi : xb) : (ab ? xa : xb);
+            const V3<R> v2 = ia ? (ab ? xb : xa) : (ib ? xb : xi);
+            // the middle one: i if it lies between a and b, else the smaller
+            // of a, b when i is the smallest and the larger when i is largest
+            const V3<R> v1 = ia != ib ? xi : (ia == ab ? xa : xb);
+            const V3<R> n = cross(sub(v1, v0), sub(v2, v0));
             const R n2 = dot(n, n);
-            L.c(0, q) = R(0.5) * cb;
-            L.c(1, q) = R(0.5) * ca;
-            L.c(2, q) = R(0.5) * sqrt(n2) / R(3);
-            if (n2 == R(0) && i < a && i < b) ++ndeg;
+            const R nn = sqrt(n2);
+            const R h = R(0.5) / nn;
+            // edge (i, a) is opposite b, edge (i, b) is opposite a
+            const R db = ia ? dot(sub(xi, xb), sub(xa, xb)) : dot(sub(xa, xb), sub(xi, xb));
+            const R da = ib ? dot(sub(xi, xa), sub(xb, xa)) : dot(sub(xb, xa), sub(xi, xa));
+            L.c(0, q) = db * h;
+            L.c(1, q) = da * h;
+            L.c(2, q) = nn / R(6);
+            if (n2 == R(0) && ia && ib) ++ndeg;
         } else {
             const int p = (int)(rec >> 24);
             const int32_t lc = base + (int32_t)((rec >> 16) & 255u);
             const int32_t w0 = L.lcol[la], w1 = L.lcol[lb], w2 = L.lcol[lc];
-            const V3<R> y0 = L.pos(la), y1 = L.pos(lb), y2 = L.pos(lc);
+            const V3<R> y0 = ld3(X, w0), y1 = ld3(X, w1), y2 = ld3(X, w2);
             // element order: i sits at position p, the others follow in order
             const V3<R> x0 = sel2v(p == 0, xi, y0);
             const V3<R> x1 = sel2v(p == 0, y0, sel2v(p == 1, xi, y1));
@@ -312,8 +316,8 @@ __device__ __forceinline__ void store_partials(const double *s_part, int W, doub
 }
 
 // Finalize sums: for w < W1, tot[w] = sum over b < n1 of p1[w * n1 + b]; for
-// W1 <= w < W1 + W2 the same over p2 (n2 partials per value). One workgroup
-// of kFinThreads threads: value w is taken by tpw consecutive threads (tpw a
+// W1 <= w < W1 + W2 the same over p2 (n2 partials per value), computed by
+// the whole workgroup: value w is taken by tpw consecutive threads (tpw a
 // power of two of at most 64, so they share a wavefront); thread `sub` adds
 // partials sub, sub + tpw, ... in order (loads issued kFinUnroll at a time),
 // and a fixed xor-shuffle tree adds the tpw subtotals. Deterministic.
@@ -323,7 +327,7 @@ __device__ void fin_sum2(const double *__restrict__ p1, int n1, int W1,
                          const double *__restrict__ p2, int n2, int W2, double *tot) {
     const int W = W1 + W2;
     int tpw = 64;
-    while (tpw > 1 && tpw * W > kFinThreads) tpw >>= 1;
+    while (tpw > 1 && tpw * W > (int)blockDim.x) tpw >>= 1;
     const int t = threadIdx.x, w = t / tpw, sub = t % tpw;
     double s = 0.0;
     if (w < W) {
@@ -435,6 +439,89 @@ __device__ __forceinline__ R row_apply(const int32_t *__restrict__ col, const R 
     if (xi) *xi = self;
     return acc;
 }
+
+// RU rows at once for one lane group, as row_apply without the mask: row u
+// is i[u] with entries [rb[u], rb[u] + len[u]) and dterm[u] on the diagonal
+// (PLAIN: the coefficients are the stored values as they are, beta and dterm
+// unused); ok[u] = false yields 0 (i[u] must still be a valid row). The entry
+// loads of all RU rows are issued before any gather, and the gathers of a
+// chunk of every row before any is used, so a lane keeps RU rows in flight.
+// Each row's sum is formed in the same order as row_apply's.
+template <typename R, int G, int KP, int RU, bool PLAIN>
+__device__ __forceinline__ void rows_apply(const int32_t *__restrict__ col,
+                                           const R *__restrict__ K, R beta, const R (&dterm)[RU],
+                                           const R *__restrict__ x, const int32_t (&i)[RU],
+                                           const int32_t (&rb)[RU], const int32_t (&len)[RU],
+                                           const bool (&ok)[RU], int k, int lane, int gbase,
+                                           R (&acc)[RU], R (&xi)[RU]) {
+    constexpr int NP = G / KP;
+    constexpr int CH0 = KP < 8 ? KP : 8;
+    constexpr int CH = CH0 / RU > 0 ? CH0 / RU : 1;  // gathers per row issued together
+    const int c = lane % KP, part = lane / KP;
+    const int cc = c < k ? c : k - 1;
+    int32_t lmax = 0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+        acc[u] = 0;
+        xi[u] = 0;
+        lmax = max(lmax, ok[u] ? len[u] : 0);
+    }
+    for (int32_t e0 = 0; e0 < lmax; e0 += G) {
+        int32_t cj[RU];
+        R aj[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            cj[u] = i[u];
+            aj[u] = 0;
+            if (ok[u] && e0 + lane < len[u]) {
+                const int32_t e = rb[u] + e0 + lane;
+                const int32_t j = col[e];
+                cj[u] = j;
+                if (PLAIN) {
+                    aj[u] = K[e];
+                } else {
+                    aj[u] = beta * K[e];
+                    if (j == i[u]) aj[u] += dterm[u];
+                }
+            }
+        }
+        if (KP == 1) {
+#pragma unroll
+            for (int u = 0; u < RU; ++u) acc[u] += aj[u] * x[cj[u]];
+        } else {
+#pragma unroll
+            for (int s0 = 0; s0 < KP; s0 += CH) {
+                int32_t js[RU][CH];
+                R xv[RU][CH];
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+#pragma unroll
+                    for (int s = 0; s < CH; ++s) js[u][s] = __shfl(cj[u], gbase + (s0 + s) * NP + part);
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+#pragma unroll
+                    for (int s = 0; s < CH; ++s) xv[u][s] = x[(int64_t)js[u][s] * k + cc];
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+#pragma unroll
+                    for (int s = 0; s < CH; ++s) {
+                        acc[u] += __shfl(aj[u], gbase + (s0 + s) * NP + part) * xv[u][s];
+                        if (NP == 1 && js[u][s] == i[u]) xi[u] = xv[u][s];
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+#pragma unroll
+        for (int off = G / 2; off >= KP; off /= 2) acc[u] += __shfl_down(acc[u], off, G);
+}
+
+// Rows of the SpMV kernels (k_spmm, k_cg_sdot) handled together by one lane
+// group. Two rows in flight were measured slower on MI355X (5% on the PCG
+// iteration, 4% on a 2.6M-row SpMV): the extra registers cost more than the
+// overlap gains.
+constexpr int kSpmvRows = 1;
 
 // Lane layout of the vector kernels: KP lanes per row, lane c owns column c.
 struct VLane {

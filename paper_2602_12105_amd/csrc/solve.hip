@@ -59,16 +59,28 @@ k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     y += bt * (int64_t)nV * k;
     const int lane = threadIdx.x % G, grp = threadIdx.x / G;
     const int gbase = (threadIdx.x & 63) - lane;
+    constexpr int RU = KP <= 8 ? kSpmvRows : 1;
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t r = tile * GPB + grp;
-        if (r >= nV) continue;  // uniform over the lane group
-        const int2 d = rdesc[r];
-        const int32_t len = rlen[r];
-        const R acc = row_apply<R, G, KP, false>(col, K, beta, alpha * M[d.x], nullptr, x, d.x,
-                                                 d.y, len, k, lane, gbase, nullptr);
-        if (lane < k && lane < KP) y[(int64_t)d.x * k + lane] = acc;
+    for (int64_t tile = t0; tile < t1; tile += RU) {
+        int32_t i[RU], rb[RU], len[RU];
+        bool ok[RU];
+        R dt[RU], acc[RU], xi[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {  // uniform over the lane group
+            const int64_t r = (tile + u) * GPB + grp;
+            ok[u] = tile + u < t1 && r < nV;
+            const int2 d = ok[u] ? rdesc[r] : make_int2(0, 0);
+            i[u] = d.x;
+            rb[u] = d.y;
+            len[u] = ok[u] ? (int32_t)rlen[r] : 0;
+            dt[u] = ok[u] ? alpha * M[d.x] : R(0);
+        }
+        if (!ok[0]) continue;
+        rows_apply<R, G, KP, RU, false>(col, K, beta, dt, x, i, rb, len, ok, k, lane, gbase, acc, xi);
+#pragma unroll
+        for (int u = 0; u < RU; ++u)
+            if (ok[u] && lane < k && lane < KP) y[(int64_t)i[u] * k + lane] = acc[u];
     }
 }
 
@@ -218,59 +230,115 @@ __global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
 k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int32_t W,
           const int32_t *__restrict__ col, int32_t nV, const R *__restrict__ v,
           const R *__restrict__ dvec, int k, const R *__restrict__ r, R *__restrict__ w,
-          double *__restrict__ part) {
+          const CgCol *__restrict__ st, double *__restrict__ part) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = TR / G;
     __shared__ double s_part[kMaxK];
     __shared__ double s_red[red_scratch(TR, 1)];
+    __shared__ int s_any;
+    if (st) {  // nothing to do once every column has stopped
+        if (threadIdx.x == 0) {
+            int any = 0;
+            for (int c = 0; c < k; ++c) any |= st[c].active;
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any) return;
+    }
     const int lane = threadIdx.x % G, grp = threadIdx.x / G;
     const int gbase = (threadIdx.x & 63) - lane;
     const bool out_lane = lane < k && lane < KP;
+    constexpr int RU = ELL && KP <= 8 ? kSpmvRows : 1;
     double dsum = 0.0;
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t pos = tile * GPB + grp;
-        if (pos >= nV) continue;  // uniform over the lane group
-        int32_t i, rb, len;
-        if (ELL) {
-            i = (int32_t)pos;
-            rb = i * W;
-            len = W;
-        } else {
-            const int2 d = rdesc[pos];
-            i = d.x;
-            rb = d.y;
-            len = rlen[pos];
+    for (int64_t tile = t0; tile < t1; tile += RU) {
+        int32_t i[RU], rb[RU], len[RU];
+        bool ok[RU];
+        R dt[RU], acc[RU], ri[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {  // uniform over the lane group
+            const int64_t pos = (tile + u) * GPB + grp;
+            ok[u] = tile + u < t1 && pos < nV;
+            if (ELL) {
+                i[u] = ok[u] ? (int32_t)pos : 0;
+                rb[u] = i[u] * W;
+                len[u] = W;
+            } else {
+                const int2 d = ok[u] ? rdesc[pos] : make_int2(0, 0);
+                i[u] = d.x;
+                rb[u] = d.y;
+                len[u] = ok[u] ? (int32_t)rlen[pos] : 0;
+            }
+            dt[u] = R(0);
         }
-        const R di = dvec[i];
-        R ri = 0;
-        const R acc = row_apply<R, G, KP, false>(col, v, R(1), R(0), nullptr, r, i, rb, len, k,
-                                                 lane, gbase, &ri);
+        if (!ok[0]) continue;
+        rows_apply<R, G, KP, RU, true>(col, v, R(1), dt, r, i, rb, len, ok, k, lane, gbase, acc, ri);
         if (out_lane) {
-            const int64_t e = (int64_t)i * k + lane;
-            w[e] = acc;
-            if (G != KP) ri = r[e];  // row_apply returns r[i, c] only when G == KP
-            dsum += (double)acc * (double)(di * ri);
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+                const int64_t e = (int64_t)i[u] * k + lane;
+                w[e] = acc[u];
+                if (G != KP) ri[u] = r[e];  // rows_apply returns r[i, c] only when G == KP
+                dsum += (double)acc[u] * (double)(dvec[i[u]] * ri[u]);
+            }
         }
     }
     column_partials(&dsum, 1, k, G, out_lane, s_red, s_part);
     store_partials(s_part, k, part);
 }
 
-// The vector work of one iteration on the active columns: p = z + beta p,
+// The vector work of iteration i on the active columns: p = z + beta p,
 // s = w + beta s, x += alpha p, r -= alpha s (z = D^-1 r), fused with partial
-// sums of r.z and r.r of the new residual.
+// sums of r.z and r.r of the new residual (stored to pout). The iteration's
+// state S_i (alpha, beta, stopping) is either read from st_cur (first
+// iteration of a chunk, computed by a finalize kernel) or, with reduce,
+// computed here from S_{i-1} (st_prev) and the partial sums of the previous
+// update (pin) and of w.z (pin2): every workgroup adds the same partials in
+// the same fixed order, so all agree bitwise, and workgroup 0 stores S_i to
+// st_cur. pin, pout and st_prev, st_cur are distinct buffers (alternating
+// with the iteration's parity), so no workgroup reads what another writes.
 template <typename R>
 __global__ void __launch_bounds__(TR)
 k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R *__restrict__ p,
              R *__restrict__ sv, const R *__restrict__ w, const R *__restrict__ invD,
-             const CgCol *__restrict__ st, double *__restrict__ part) {
+             const CgCol *__restrict__ st_prev, CgCol *__restrict__ st_cur, int reduce,
+             const double *__restrict__ pin, int nbu, const double *__restrict__ pin2, int nbs,
+             double *__restrict__ pout, CgParams prm) {
     __shared__ double s_part[2 * kMaxK];
     __shared__ double s_red[red_scratch(TR, 2)];
+    __shared__ double s_tot[3 * kMaxK];
+    __shared__ double s_ab[2 * kMaxK];
+    __shared__ int s_on[kMaxK];
+    __shared__ int s_any;
+    const int t = threadIdx.x;
+    const CgCol *sin = reduce ? st_prev : st_cur;
+    if (t == 0) {
+        int any = 0;
+        for (int c = 0; c < k; ++c) any |= sin[c].active;
+        s_any = any;
+    }
+    __syncthreads();
+    if (!s_any) {  // every column has stopped: the state carries over
+        if (reduce && blockIdx.x == 0 && t < k) st_cur[t] = st_prev[t];
+        return;
+    }
+    if (reduce) fin_sum2(pin, nbu, 2 * k, pin2, nbs, k, s_tot);
+    if (t < k) {
+        CgCol c = reduce ? st_prev[t] : st_cur[t];
+        if (reduce) {
+            cg_sr_update(FIN_SR_ITER, c, s_tot, s_tot + 2 * k, t, k, prm);
+            if (blockIdx.x == 0) st_cur[t] = c;
+        }
+        s_on[t] = c.active;
+        s_ab[t] = c.alpha;
+        s_ab[k + t] = c.beta;
+    }
+    __syncthreads();
     const VLane L = vlane(k, KP);
-    const bool on = L.act && st[L.c].active;
-    const R a = on ? (R)st[L.c].alpha : R(0), bt = on ? (R)st[L.c].beta : R(0);
+    const bool on = L.act && s_on[L.c];
+    const R a = on ? (R)s_ab[L.c] : R(0), bt = on ? (R)s_ab[k + L.c] : R(0);
     double d[2] = {0.0, 0.0};
     int64_t t0, t1;
     tile_range(((int64_t)nV + L.gpb - 1) / L.gpb, t0, t1);
@@ -293,30 +361,29 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
         }
     }
     column_partials(d, 2, k, KP, on, s_red, s_part);
-    store_partials(s_part, 2 * k, part);
+    store_partials(s_part, 2 * k, pout);
 }
 
-// One workgroup: add the partial sums of the preceding kernel(s) in a fixed
-// order, then update the per-column state (or store the totals). The
-// one-reduction modes also add a second array of k values (w.z).
+// One workgroup: add the partial sums of the preceding kernels in a fixed
+// order and advance the per-column state from st_in to st_out (FIN_SR_INIT:
+// a fresh state), or store the totals to out (FIN_OUT).
 template <int MODE>
 __global__ void __launch_bounds__(kFinThreads)
 k_cg_fin(const double *__restrict__ part, int nblk, const double *__restrict__ part2, int nblk2,
-         int k, CgCol *st, CgParams prm, double *out) {
+         int k, const CgCol *st_in, CgCol *st_out, CgParams prm, double *out) {
     __shared__ double s_tot[4 * kMaxK];
     constexpr bool SR = MODE == FIN_SR_INIT || MODE == FIN_SR_ITER;
     const int W = fin_width(MODE, k);
     fin_sum2(part, nblk, W, part2, nblk2, SR ? k : 0, s_tot);
     const int c = threadIdx.x;
     if (c >= k) return;
-    if (MODE == FIN_OUT) {
+    if (!SR) {
         out[c] = s_tot[c];
         return;
     }
-    if (SR)
-        cg_sr_update(MODE, st[c], s_tot, s_tot + W, c, k, prm);
-    else
-        cg_state_update(MODE, st[c], s_tot, c, k, prm);
+    CgCol st = MODE == FIN_SR_INIT ? CgCol{} : st_in[c];
+    cg_sr_update(MODE, st, s_tot, s_tot + W, c, k, prm);
+    st_out[c] = st;
 }
 
 // 1 / (alpha M_ii + beta K_ii); zero on masked rows.
@@ -453,39 +520,40 @@ int launch_cg_spmm(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
 }
 
 template <int MODE>
-void launch_fin(const double *part, int nblk, const double *part2, int nblk2, int k, CgCol *st,
-                CgParams prm, double *out, hipStream_t s) {
+void launch_fin(const double *part, int nblk, const double *part2, int nblk2, int k,
+                const CgCol *st_in, CgCol *st_out, CgParams prm, double *out, hipStream_t s) {
     DGO_LAUNCH("cg_fin", s,
-               k_cg_fin<MODE><<<1, kFinThreads, 0, s>>>(part, nblk, part2, nblk2, k, st, prm, out));
+               k_cg_fin<MODE><<<1, kFinThreads, 0, s>>>(part, nblk, part2, nblk2, k, st_in, st_out,
+                                                        prm, out));
 }
 
 template <typename R, int KP>
 int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R *r, R *w,
-                   double *part, hipStream_t s) {
+                   const CgCol *st, double *part, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
     const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), kMaxRedBlocks);
     if (m->ell_w)
         DGO_LAUNCH("cg_sdot", s,
                    k_cg_sdot<R, KP, true><<<nb, TR, 0, s>>>(nullptr, nullptr, m->ell_w, m->ell_col,
-                                                            m->nV, v, dvec, k, r, w, part));
+                                                            m->nV, v, dvec, k, r, w, st, part));
     else
         DGO_LAUNCH("cg_sdot", s,
                    k_cg_sdot<R, KP, false><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, 0, m->col, m->nV, v,
-                                                             dvec, k, r, w, part));
+                                                             dvec, k, r, w, st, part));
     return (int)nb;
 }
 
 template <typename R>
 int launch_sdot(const dgo_mesh *m, const R *v, const R *dvec, int k, const R *r, R *w,
-                double *part, hipStream_t s) {
+                const CgCol *st, double *part, hipStream_t s) {
     switch (pow2ceil(k)) {
-        case 1: return launch_sdot_kp<R, 1>(m, v, dvec, k, r, w, part, s);
-        case 2: return launch_sdot_kp<R, 2>(m, v, dvec, k, r, w, part, s);
-        case 4: return launch_sdot_kp<R, 4>(m, v, dvec, k, r, w, part, s);
-        case 8: return launch_sdot_kp<R, 8>(m, v, dvec, k, r, w, part, s);
-        case 16: return launch_sdot_kp<R, 16>(m, v, dvec, k, r, w, part, s);
-        case 32: return launch_sdot_kp<R, 32>(m, v, dvec, k, r, w, part, s);
-        default: return launch_sdot_kp<R, 64>(m, v, dvec, k, r, w, part, s);
+        case 1: return launch_sdot_kp<R, 1>(m, v, dvec, k, r, w, st, part, s);
+        case 2: return launch_sdot_kp<R, 2>(m, v, dvec, k, r, w, st, part, s);
+        case 4: return launch_sdot_kp<R, 4>(m, v, dvec, k, r, w, st, part, s);
+        case 8: return launch_sdot_kp<R, 8>(m, v, dvec, k, r, w, st, part, s);
+        case 16: return launch_sdot_kp<R, 16>(m, v, dvec, k, r, w, st, part, s);
+        case 32: return launch_sdot_kp<R, 32>(m, v, dvec, k, r, w, st, part, s);
+        default: return launch_sdot_kp<R, 64>(m, v, dvec, k, r, w, st, part, s);
     }
 }
 
@@ -505,9 +573,9 @@ PcgLayout pcg_layout(int64_t nV, int64_t nvals, int k, size_t elem) {
     L.off_dp = L.off_d + al(elem * (size_t)nV);
     L.off_v = L.off_dp + al(elem * (size_t)nV);
     L.off_pt = L.off_v + al(elem * (size_t)nvals);
-    L.off_pt2 = L.off_pt + al(sizeof(double) * kern::kMaxRedBlocks * 3 * kern::kMaxK);
+    L.off_pt2 = L.off_pt + 2 * al(sizeof(double) * kern::kMaxRedBlocks * 3 * kern::kMaxK);
     L.off_st = L.off_pt2 + al(sizeof(double) * kern::kMaxRedBlocks * kern::kMaxK);
-    L.off_tr = L.off_st + al(sizeof(kern::CgCol) * kern::kMaxK);
+    L.off_tr = L.off_st + 2 * al(sizeof(kern::CgCol) * kern::kMaxK);
     L.total = L.off_tr + al(sizeof(double) * kern::kMaxK);
     return L;
 }
@@ -535,8 +603,14 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     R *invD = (R *)(ws + L.off_d);                     // natural order
     R *dvec = ell ? (R *)(ws + L.off_dp) : invD;       // the loop's order
     R *v = (R *)(ws + L.off_v);
-    double *part = (double *)(ws + L.off_pt), *part2 = (double *)(ws + L.off_pt2);
-    CgCol *st = (CgCol *)(ws + L.off_st);
+    // partU[i & 1]: partials of the update that precedes iteration i;
+    // stt[i & 1]: the state S_i of iteration i
+    const size_t pu_stride = ((sizeof(double) * kMaxRedBlocks * 3 * kMaxK + 255) & ~(size_t)255);
+    const size_t st_stride = ((sizeof(CgCol) * kMaxK + 255) & ~(size_t)255);
+    double *partU[2] = {(double *)(ws + L.off_pt), (double *)(ws + L.off_pt + pu_stride)};
+    double *part2 = (double *)(ws + L.off_pt2);
+    CgCol *stt[2] = {(CgCol *)(ws + L.off_st), (CgCol *)(ws + L.off_st + st_stride)};
+    double *part = partU[0];
     double *tr = (double *)(ws + L.off_tr);
     const size_t total = L.total;
 
@@ -571,89 +645,76 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     DGO_LAUNCH("cg_init", s,
                k_cg_init<R><<<nb_v, TR, 0, s>>>((int32_t)nV, k, KP, ell ? m->order : nullptr, beff,
                                                 w, u, ell ? x : nullptr, dvec, r, p, sv, part));
-    int nb_s = launch_sdot<R>(m, v, dvec, k, r, w, part2, s);
-    launch_fin<FIN_SR_INIT>(part, (int)nb_v, part2, nb_s, k, st, prm, nullptr, s);
+    int nb_s = launch_sdot<R>(m, v, dvec, k, r, w, nullptr, part2, s);
+    launch_fin<FIN_SR_INIT>(part, (int)nb_v, part2, nb_s, k, nullptr, stt[0], prm, nullptr, s);
     DGO_HIP(hipGetLastError());
 
     const int every = o.fixed_iters ? (o.max_iter > 0 ? o.max_iter : 1)
                                     : (o.check_every > 0 ? o.check_every : 8);
-    // one reduction per iteration: vector update, w = A z with w.z, finalize
-    auto iterate = [&](hipStream_t st_s, int32_t count) {
+    // Iterations i0 .. i0 + count - 1, then a finalize that leaves the state
+    // of iteration i0 + count for the host. Each iteration is two kernels:
+    // the vector update (which also finishes the previous iteration's
+    // reductions, except in the first iteration of a chunk, whose state the
+    // finalize before it computed) and w = A z with w.z.
+    auto iterate = [&](hipStream_t st_s, int32_t i0, int32_t count) {
+        int nbs = nb_s;
         for (int32_t it = 0; it < count; ++it) {
+            const int32_t i = i0 + it;
             DGO_LAUNCH("cg_vupdate", st_s,
-                       k_cg_vupdate<R><<<nb_v, TR, 0, st_s>>>((int32_t)nV, k, KP, x, r, p, sv, w, dvec,
-                                                             st, part));
-            const int nbs = launch_sdot<R>(m, v, dvec, k, r, w, part2, st_s);
-            launch_fin<FIN_SR_ITER>(part, (int)nb_v, part2, nbs, k, st, prm, nullptr, st_s);
+                       k_cg_vupdate<R><<<nb_v, TR, 0, st_s>>>(
+                           (int32_t)nV, k, KP, x, r, p, sv, w, dvec, stt[(i + 1) & 1], stt[i & 1],
+                           it > 0 ? 1 : 0, partU[i & 1], (int)nb_v, part2, nbs, partU[(i + 1) & 1],
+                           prm));
+            nbs = launch_sdot<R>(m, v, dvec, k, r, w, stt[i & 1], part2, st_s);
         }
+        const int32_t e = i0 + count;
+        launch_fin<FIN_SR_ITER>(partU[e & 1], (int)nb_v, part2, nbs, k, stt[(e + 1) & 1], stt[e & 1],
+                                prm, nullptr, st_s);
     };
-    // Opt-in (DGO_PCG_GRAPH=1): replay full chunks from a graph when the same
-    // arguments repeat. Measured slower than direct launches on MI355X (the
-    // replay on a second stream adds two event joins per chunk), so it is off
-    // by default; tracing also disables it.
-    const bool graphs = !trace_active() && getenv("DGO_PCG_GRAPH") && atoi(getenv("DGO_PCG_GRAPH")) > 0;
-    uint64_t key[24] = {(uint64_t)(uintptr_t)M, (uint64_t)(uintptr_t)K, (uint64_t)(uintptr_t)mask,
-                        (uint64_t)(uintptr_t)u, (uint64_t)(uintptr_t)ws, (uint64_t)total,
-                        (uint64_t)k, (uint64_t)every, (uint64_t)sizeof(R), nb_v, (uint64_t)nb_s,
-                        0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1};
-    memcpy(&key[11], &alpha, 8);
-    memcpy(&key[12], &beta, 8);
-    memcpy(&key[13], &prm.rtol, 8);
-    key[14] = (uint64_t)(uint32_t)prm.max_iter | ((uint64_t)(uint32_t)prm.fixed << 32);
-    key[15] = (uint64_t)(uint32_t)prm.stall;
+    // Progress polling without idling the device: chunk n + 1 is queued
+    // before the host waits for the state copied after chunk n, so the
+    // device never waits for the host's check. Once every column has stopped,
+    // the queued chunk finds no active column and does next to nothing.
     dgo_mesh *mm = const_cast<dgo_mesh *>(m);
-    CgCol hst[kMaxK];
+    if (!mm->poll_host) {
+        DGO_HIP(hipHostMalloc(&mm->poll_host, 2 * sizeof(CgCol) * kMaxK, hipHostMallocDefault));
+        for (auto &e : mm->poll_ev) DGO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    CgCol *hpoll = (CgCol *)mm->poll_host;
     int32_t done_iters = 0;
+    int prev = -1;  // slot of the last queued chunk whose state is unchecked
     for (;;) {
         const int32_t chunk = std::min(every, o.max_iter - done_iters);
-        if (chunk <= 0) break;
-        if (graphs && chunk == every) {
-            if (!mm->graph_stream) {
-                DGO_HIP(hipStreamCreateWithFlags(&mm->graph_stream, hipStreamNonBlocking));
-                DGO_HIP(hipEventCreateWithFlags(&mm->graph_ev[0], hipEventDisableTiming));
-                DGO_HIP(hipEventCreateWithFlags(&mm->graph_ev[1], hipEventDisableTiming));
-            }
-            hipStream_t gs = mm->graph_stream;
-            if (!mm->graph || memcmp(mm->graph_key, key, sizeof key) != 0) {
-                mesh_drop_graph(mm);
-                hipGraph_t g = nullptr;
-                DGO_HIP(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-                iterate(gs, chunk);
-                DGO_HIP(hipStreamEndCapture(gs, &g));
-                hipError_t e = hipGraphInstantiate(&mm->graph, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (e != hipSuccess) {
-                    mm->graph = nullptr;
-                    return hip_fail(e, "hipGraphInstantiate", __FILE__, __LINE__);
-                }
-                memcpy(mm->graph_key, key, sizeof key);
-            }
-            DGO_HIP(hipEventRecord(mm->graph_ev[0], s));
-            DGO_HIP(hipStreamWaitEvent(gs, mm->graph_ev[0], 0));
-            DGO_HIP(hipGraphLaunch(mm->graph, gs));
-            DGO_HIP(hipEventRecord(mm->graph_ev[1], gs));
-            DGO_HIP(hipStreamWaitEvent(s, mm->graph_ev[1], 0));
-        } else {
-            iterate(s, chunk);
+        int cur = -1;
+        if (chunk > 0) {
+            cur = prev == 0 ? 1 : 0;
+            iterate(s, done_iters, chunk);
+            done_iters += chunk;
+            DGO_HIP(hipMemcpyAsync(hpoll + cur * kMaxK, stt[done_iters & 1], sizeof(CgCol) * k,
+                                   hipMemcpyDeviceToHost, s));
+            DGO_HIP(hipEventRecord(mm->poll_ev[cur], s));
+            DGO_HIP(hipGetLastError());
         }
-        DGO_HIP(hipGetLastError());
-        done_iters += chunk;
-        DGO_HIP(hipMemcpyAsync(hst, st, sizeof(CgCol) * k, hipMemcpyDeviceToHost, s));
-        DGO_HIP(hipStreamSynchronize(s));
-        bool any = false;
-        for (int c = 0; c < k; ++c) any = any || hst[c].active;
-        if (!any) break;
+        if (prev >= 0) {
+            DGO_HIP(hipEventSynchronize(mm->poll_ev[prev]));
+            bool any = false;
+            for (int c = 0; c < k; ++c) any = any || hpoll[prev * kMaxK + c].active;
+            if (!any) break;
+        }
+        if (cur < 0) break;
+        prev = cur;
     }
+    CgCol hst[kMaxK];
     if (ell)
         DGO_LAUNCH("cg_unorder", s,
                    k_cg_unorder<R><<<grid_for(n, T), T, 0, s>>>(n, k, m->order, x, u));
     DGO_LAUNCH("cg_trueres", s,
                k_cg_trueres<R><<<nb_v, TR, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta, K,
                                                   mask, k, KP, beff, u, part));
-    launch_fin<FIN_OUT>(part, (int)nb_v, nullptr, 0, k, st, prm, tr, s);
+    launch_fin<FIN_OUT>(part, (int)nb_v, nullptr, 0, k, nullptr, nullptr, prm, tr, s);
     DGO_HIP(hipGetLastError());
     double htr[kMaxK];
-    DGO_HIP(hipMemcpyAsync(hst, st, sizeof(CgCol) * k, hipMemcpyDeviceToHost, s));
+    DGO_HIP(hipMemcpyAsync(hst, stt[done_iters & 1], sizeof(CgCol) * k, hipMemcpyDeviceToHost, s));
     DGO_HIP(hipMemcpyAsync(htr, tr, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     DGO_HIP(hipStreamSynchronize(s));
     bool all = true;

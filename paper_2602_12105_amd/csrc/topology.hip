@@ -612,12 +612,11 @@ static dgo_status build_row_desc(dgo_mesh *m, hipStream_t s, bool bfs) {
 }
 
 static void release(dgo_mesh *m, hipStream_t s) {
-    mesh_drop_graph(m);
-    if (m->graph_ev[0]) (void)hipEventDestroy(m->graph_ev[0]);
-    if (m->graph_ev[1]) (void)hipEventDestroy(m->graph_ev[1]);
-    if (m->graph_stream) (void)hipStreamDestroy(m->graph_stream);
-    m->graph_ev[0] = m->graph_ev[1] = nullptr;
-    m->graph_stream = nullptr;
+    for (auto &e : m->poll_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (m->poll_host) (void)hipHostFree(m->poll_host);
+    m->poll_ev[0] = m->poll_ev[1] = nullptr;
+    m->poll_host = nullptr;
     void *ptrs[] = {m->elem, m->EV, m->elem_edge, m->elem_sign, m->rowptr, m->col,
                     m->diag, m->vtptr, m->inc, m->bmask, m->rdesc, m->rlen, m->order,
                     m->ell_col, m->ell_src, m->ws};
