@@ -116,6 +116,7 @@ struct dgo_mesh {
     int32_t nblocks = 0;        // ceil(nV / rpb)
     int32_t max_block_nnz = 0;  // largest CSR span of one block of rows
     int32_t max_block_inc = 0;  // most incidence records of one block of rows
+    int64_t lds_budget = 0;     // LDS bytes a row block may take (0: kRowBlockLdsBytes)
 
     // scratch workspace reused by numeric calls (grows on demand)
     void *ws = nullptr;
@@ -141,9 +142,11 @@ bool trace_active();
 enum RowsMode { ROWS_NONE = 0, ROWS_NATURAL = 1, ROWS_AUTO = 2 };
 constexpr int32_t kRowOrderMinRows = 16384;
 constexpr int32_t kEllMaxWidth = 16;
+// lds_budget: the LDS bytes one row block of the assembly may take (0: the
+// default, kRowBlockLdsBytes); rows per block are halved until it fits.
 dgo_status mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_t *d_elem,
                        const dgo_allocator *alloc, hipStream_t s, RowsMode rows,
-                       dgo_mesh **out);
+                       int64_t lds_budget, dgo_mesh **out);
 
 // Workspace of one PCG solve (byte offsets): vectors r, p, s, w, the
 // effective right-hand side and x in row order, D^-1 in natural and in row

@@ -440,6 +440,55 @@ __device__ __forceinline__ R row_apply(const int32_t *__restrict__ col, const R 
     return acc;
 }
 
+// Padded rows of at most G entries (slots [i W, i W + W), W <= G), split in
+// two so that a caller can load the next row's entries while the current
+// row's gathers are in flight: ell_entry loads the lane's entry (column,
+// value), padding and lanes past W giving (i, 0); ell_row forms the row from
+// those entries exactly as row_apply does (same operations, same order).
+template <typename R>
+__device__ __forceinline__ void ell_entry(const int32_t *__restrict__ col, const R *__restrict__ v,
+                                          int32_t W, int32_t i, int lane, int32_t &cj, R &aj) {
+    cj = i;
+    aj = R(0);
+    if (lane < W) {
+        const int64_t e = (int64_t)i * W + lane;
+        cj = col[e];
+        aj = v[e];
+    }
+}
+
+template <typename R, int G, int KP>
+__device__ __forceinline__ R ell_row(int32_t cj, R aj, const R *__restrict__ x, int32_t i, int k,
+                                     int lane, int gbase, R *xi) {
+    constexpr int NP = G / KP;
+    constexpr int CH = KP < 8 ? KP : 8;
+    const int c = lane % KP, part = lane / KP;
+    const int cc = c < k ? c : k - 1;
+    R acc = 0, self = 0;
+    if (KP == 1) {
+        acc += aj * x[cj];
+    } else {
+#pragma unroll
+        for (int s0 = 0; s0 < KP; s0 += CH) {
+            int32_t js[CH];
+            R xv[CH];
+#pragma unroll
+            for (int s = 0; s < CH; ++s) js[s] = __shfl(cj, gbase + (s0 + s) * NP + part);
+#pragma unroll
+            for (int s = 0; s < CH; ++s) xv[s] = x[(int64_t)js[s] * k + cc];
+#pragma unroll
+            for (int s = 0; s < CH; ++s) {
+                acc += __shfl(aj, gbase + (s0 + s) * NP + part) * xv[s];
+                if (NP == 1 && js[s] == i) self = xv[s];
+            }
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off >= KP; off /= 2) acc += __shfl_down(acc, off, G);
+    if (xi) *xi = self;
+    return acc;
+}
+
 // RU rows at once for one lane group, as row_apply without the mask: row u
 // is i[u] with entries [rb[u], rb[u] + len[u]) and dterm[u] on the diagonal
 // (PLAIN: the coefficients are the stored values as they are, beta and dterm

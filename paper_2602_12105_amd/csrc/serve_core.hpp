@@ -8,9 +8,14 @@
 //   dgo_status prepare(Req &r)                 // after admission, on a prep thread
 //   dgo_status tick(std::vector<Req *> &active, int32_t chunk)
 //       runs up to `chunk` iterations of every active request (a request's
-//       first tick also assembles and initialises it); sets r.done_iters
+//       first tick also assembles and initialises it) and returns when that
+//       work is complete; sets r.done_iters
 //   dgo_status finish(Req &r)                  // copy the result to the host
 //   void release(Req &r)                       // drop per-request device state
+// finish and release run on a completion thread, concurrently with the next
+// tick (which no longer includes the request), so result copies overlap the
+// device's work; the request keeps its slot and memory until it is retired
+// after them.
 #pragma once
 
 #include <algorithm>
@@ -107,6 +112,7 @@ class Scheduler {
         free_slots_.resize(o_.max_slots);
         for (int i = 0; i < o_.max_slots; ++i) free_slots_[i] = o_.max_slots - 1 - i;
         run_ = std::thread([this] { schedule_loop(); });
+        done_ = std::thread([this] { complete_loop(); });
         for (int i = 0; i < std::max(1, o_.prep_threads); ++i)
             prep_.emplace_back([this] { prep_loop(); });
     }
@@ -183,6 +189,7 @@ class Scheduler {
         for (auto &t : prep_)
             if (t.joinable()) t.join();
         if (run_.joinable()) run_.join();
+        if (done_.joinable()) done_.join();
     }
 
     Arena &arena() { return arena_; }
@@ -254,7 +261,11 @@ class Scheduler {
                     return !ready_.empty() || !active.empty() ||
                            (stopping_ && queue_.empty() && n_admitted_ == 0);
                 });
-                if (ready_.empty() && active.empty()) return;
+                if (ready_.empty() && active.empty()) {
+                    sched_done_ = true;
+                    cv_.notify_all();
+                    return;
+                }
                 const double t = now_s();
                 while (!ready_.empty()) {
                     Req *q = ready_.front();
@@ -267,30 +278,49 @@ class Scheduler {
             const double t0 = now_s();
             const int32_t chunk = o_.cg_chunk > 0 ? o_.cg_chunk : o_.cg_iters;
             const dgo_status s = ex_.tick(active, chunk);
-            std::vector<Req *> keep;
-            std::vector<std::pair<Req *, bool>> retire;
+            std::vector<Req *> keep, out;
             for (Req *q : active) {
                 q->initialised = true;
                 q->iters = q->done_iters;
                 if (s != DGO_OK) {
                     q->status = s;
-                    retire.push_back({q, false});
+                    out.push_back(q);
                 } else if (q->done_iters >= q->target) {
-                    const dgo_status f = ex_.finish(*q);
-                    q->status = f;
-                    retire.push_back({q, f == DGO_OK});
+                    q->status = DGO_OK;
+                    out.push_back(q);
                 } else {
                     keep.push_back(q);
                 }
             }
             const double t1 = now_s();
-            for (auto &rq : retire) ex_.release(*rq.first);
             std::lock_guard<std::mutex> lk(mu_);
             busy_s_ += t1 - t0;
             st_.ticks++;
             st_.max_batch = std::max<int64_t>(st_.max_batch, (int64_t)active.size());
-            for (auto &rq : retire) retire_locked(rq.first, rq.second);
+            for (Req *q : out) completing_.push_back(q);
+            if (!out.empty()) cv_.notify_all();
             active.swap(keep);
+        }
+    }
+
+    // Completion thread: copy results out and release the requests that the
+    // scheduler finished (or that a failed tick ended), then retire them.
+    void complete_loop() {
+        for (;;) {
+            Req *q = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return !completing_.empty() || sched_done_; });
+                if (completing_.empty()) return;  // the scheduler has stopped
+                q = completing_.front();
+                completing_.pop_front();
+            }
+            const bool ran = q->status == DGO_OK;
+            const dgo_status f = ran ? ex_.finish(*q) : (dgo_status)q->status;
+            ex_.release(*q);
+            std::lock_guard<std::mutex> lk(mu_);
+            q->status = f;
+            retire_locked(q, f == DGO_OK);
         }
     }
 
@@ -299,15 +329,15 @@ class Scheduler {
     Arena arena_;
     std::mutex mu_;
     std::condition_variable cv_, done_cv_;
-    std::deque<Req *> queue_, ready_;
+    std::deque<Req *> queue_, ready_, completing_;
     std::vector<int> free_slots_;
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs_;
     uint64_t next_ticket_ = 0;
     int n_admitted_ = 0;
-    bool stopping_ = false;
+    bool stopping_ = false, sched_done_ = false;
     double busy_s_ = 0;
     dgo_server_counters st_{};
-    std::thread run_;
+    std::thread run_, done_;
     std::vector<std::thread> prep_;
 };
 

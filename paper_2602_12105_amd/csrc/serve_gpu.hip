@@ -4,14 +4,16 @@
 // Batched execution. Every active request is described by a SrvDesc (its
 // topology, its device arrays and this tick's plan) in one device array that
 // is rewritten before each tick. The kernels are persistent: a fixed grid
-// walks the concatenated row tiles of all active requests, looks up the
-// request a tile belongs to by binary search over the requests' tile
-// offsets, and runs that request's tile with the same per-tile code as the
-// per-mesh kernels. One tick is: assembly and solver start for requests that
-// joined, then `cg_chunk` PCG iterations (SpMM with p.q, finalize alpha,
-// residual update with r.z and r.r, finalize beta, x and p update) for every
-// request that still has iterations left. The launch sequence of a tick never
-// changes, so it is captured once as a graph and replayed every tick.
+// splits the concatenated row tiles of all active requests into contiguous
+// ranges, one per workgroup; a workgroup finds the request of its first tile
+// by binary search over the requests' tile offsets and steps to the next
+// request as its range crosses into it, and runs each tile with the same
+// per-tile code as the per-mesh kernels. One tick is: assembly and solver
+// start for requests that joined, then `cg_chunk` PCG iterations (the
+// one-reduction form of the per-mesh solver: vector update with r.z and r.r,
+// w = A D^-1 r with w.z, per-request finalize) for every request that still
+// has iterations left. The launch sequence of a tick never changes, so it is
+// captured once as a graph and replayed every tick.
 //
 // A request's tiles, partial sums and reduction order depend only on the
 // request, so its result is bitwise the same alone or in any batch.
@@ -32,20 +34,30 @@ using namespace kern;
 using R = float;
 
 constexpr int kSrvBlocks = 2048;      // persistent grid of the batched streaming kernels
-constexpr int kSrvAsmBlocks = 1024;   // persistent grid of the batched assembly
+constexpr int kSrvAsmBlocks = 2048;   // persistent grid of the batched assembly
 constexpr int kSrvMaxSlots = 256;
 constexpr int kSrvMaxK = 16;
+// Row tiles per work unit of the batched streaming kernels: a workgroup runs
+// a unit's tiles back to back, adding each thread's terms in registers, and
+// reduces once per unit (the unit is fixed per request, so the sums do not
+// depend on the batch).
+constexpr int kSrvTilesPerUnit = 8;
+// LDS of one assembly row block: eight resident workgroups per CU (a row
+// block of 64 rows of a mesh of degree up to about 8 needs less in FP32).
+constexpr int64_t kSrvLdsBytes = 20 * 1024;
 
 struct SrvDesc {
     AsmView view;
     const int32_t *diag;
+    const int32_t *ell_col, *ell_src;  // padded rows in natural order (ell_w = 0: none)
     int64_t nnz;
+    int32_t ell_w, pad0;
     const R *X, *f;
-    R *K, *M, *u, *r, *p, *q, *invD;
-    double *part;
+    R *K, *M, *u, *r, *p, *s, *w, *invD, *v;
+    double *part, *part2;
     CgCol *st;
     int32_t k, KP, init, iters;
-    int32_t tiles_s, tiles_v, off_a, off_s, off_v, nblocks;
+    int32_t tiles_s, tiles_v, units_s, units_v, off_a, off_s, off_v, nblocks;
 };
 
 struct SrvHdr {
@@ -69,32 +81,43 @@ __device__ __forceinline__ int find_req(const SrvDesc *d, int n, int32_t v, int 
     return lo;
 }
 
-__global__ void __launch_bounds__(kAssembleThreads)
-ks_assemble(const SrvHdr *hdr, const SrvDesc *d, int32_t *ndeg) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int n = hdr->n, tot = hdr->tot_a;
-    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
-        const SrvDesc &q = d[find_req(d, n, v, SP_A)];
-        assemble_block<R, 2>(q.view, (uint32_t)(v - q.off_a), q.X, q.K, q.M, 0, R(0), ndeg, smem);
+// Calls f(request, unit of the request) for each unit of this workgroup's
+// contiguous range of the tick's units in space sp (SP_A: one assembly row
+// block per unit). Uniform over the workgroup (f may synchronise).
+template <class F>
+__device__ __forceinline__ void for_tiles(const SrvDesc *d, int n, int32_t tot, int sp, F &&f) {
+    int64_t t0, t1;
+    tile_range(tot, t0, t1);
+    if (t0 >= t1) return;
+    int r = find_req(d, n, (int32_t)t0, sp);
+    for (int32_t v = (int32_t)t0; v < (int32_t)t1; ++v) {
+        while (r + 1 < n && off_of(d[r + 1], sp) <= v) ++r;
+        f(d[r], v - off_of(d[r], sp));
     }
 }
 
-// Start of the solve (x0 = 0): D^-1, b = M f, r = b, p = D^-1 r; partial sums
-// of r.z, r.r, b.b.
+__global__ void __launch_bounds__(kAssembleThreads)
+ks_assemble(const SrvHdr *hdr, const SrvDesc *d, int32_t *ndeg) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for_tiles(d, hdr->n, hdr->tot_a, SP_A, [&](const SrvDesc &q, int32_t tile) {
+        assemble_block<R, 2>(q.view, (uint32_t)tile, q.X, q.K, q.M, 0, R(0), ndeg, smem);
+    });
+}
+
+// Start of the solve (x0 = 0): D^-1, b = M f, r = b, p = s = 0; partial sums
+// of r.z, r.r, b.b per unit.
 __global__ void __launch_bounds__(T)
 ks_init(const SrvHdr *hdr, const SrvDesc *d, R alpha, R beta) {
     __shared__ double s_part[3 * kSrvMaxK];
     __shared__ double s_red[red_scratch(T, 3)];
-    const int n = hdr->n, tot = hdr->tot_v;
-    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
-        const SrvDesc &q = d[find_req(d, n, v, SP_V)];
-        if (!q.init) continue;
-        const int32_t tile = v - q.off_v;
+    for_tiles(d, hdr->n, hdr->tot_v, SP_V, [&](const SrvDesc &q, int32_t unit) {
+        if (!q.init) return;
         const VLane L = vlane(q.k, q.KP);
-        const int64_t i = (int64_t)tile * L.gpb + L.grp;
-        const bool on = L.act && i < q.view.nV;
         double dd[3] = {0.0, 0.0, 0.0};
-        if (on) {
+        const int32_t tb = unit * kSrvTilesPerUnit, te = min(tb + kSrvTilesPerUnit, q.tiles_v);
+        for (int32_t tile = tb; tile < te; ++tile) {
+            const int64_t i = (int64_t)tile * L.gpb + L.grp;
+            if (!L.act || i >= q.view.nV) continue;
             const R inv = R(1) / (alpha * q.M[i] + beta * q.K[q.diag[i]]);
             if (L.c == 0) q.invD[i] = inv;
             const int64_t e = i * q.k + L.c;
@@ -102,129 +125,189 @@ ks_init(const SrvHdr *hdr, const SrvDesc *d, R alpha, R beta) {
             const R z = inv * b;
             q.u[e] = R(0);
             q.r[e] = b;
-            q.p[e] = z;
-            dd[0] = (double)b * (double)z;
-            dd[1] = (double)b * (double)b;
-            dd[2] = dd[1];
+            q.p[e] = R(0);
+            q.s[e] = R(0);
+            dd[0] += (double)b * (double)z;
+            dd[1] += (double)b * (double)b;
         }
-        column_partials(dd, 3, q.k, q.KP, on, s_red, s_part);
+        dd[2] = dd[1];
+        column_partials(dd, 3, q.k, q.KP, L.act, s_red, s_part);
         const int W = 3 * q.k;
-        if ((int)threadIdx.x < W) q.part[(size_t)threadIdx.x * q.tiles_v + tile] = s_part[threadIdx.x];
+        if ((int)threadIdx.x < W) q.part[(size_t)threadIdx.x * q.units_v + unit] = s_part[threadIdx.x];
         __syncthreads();
-    }
+    });
+}
+
+// Operator values scaled by the preconditioner, v_ij = A_ij d_j (after
+// ks_init has stored D^-1), in padded-row layout when the request has one
+// (padding 0), else aligned with the CSR entries.
+__global__ void __launch_bounds__(T)
+ks_values(const SrvHdr *hdr, const SrvDesc *d, R alpha, R beta) {
+    for_tiles(d, hdr->n, hdr->tot_a, SP_A, [&](const SrvDesc &q, int32_t tile) {
+        const int32_t r0 = tile * q.view.rpb, r1 = min(r0 + q.view.rpb, q.view.nV);
+        if (q.ell_w) {
+            const int32_t W = q.ell_w;
+            for (int32_t e = r0 * W + (int32_t)threadIdx.x; e < r1 * W; e += blockDim.x) {
+                const int32_t t = q.ell_src[e];
+                R val = R(0);
+                if (t >= 0) {
+                    const int32_t j = q.view.col[t];
+                    R a = beta * q.K[t];
+                    if (q.diag[j] == t) a += alpha * q.M[j];  // the diagonal entry
+                    val = a * q.invD[j];
+                }
+                q.v[e] = val;
+            }
+            return;
+        }
+        const int32_t s0 = q.view.rowptr[r0], s1 = q.view.rowptr[r1];
+        for (int32_t t = s0 + (int32_t)threadIdx.x; t < s1; t += blockDim.x) {
+            const int32_t j = q.view.col[t];
+            R a = beta * q.K[t];
+            if (q.diag[j] == t) a += alpha * q.M[j];  // the diagonal entry of row j = i
+            q.v[t] = a * q.invD[j];
+        }
+    });
 }
 
 template <int KP>
-__device__ __forceinline__ void spmm_tile(const SrvDesc &q, int32_t tile, R alpha, R beta,
-                                          double *s_red, double *s_part) {
+__device__ __forceinline__ void sdot_unit(const SrvDesc &q, int32_t unit, double *s_red,
+                                          double *s_part) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = T / G;
     const int lane = threadIdx.x % G, grp = threadIdx.x / G;
     const int gbase = (threadIdx.x & 63) - lane;
-    const int32_t row = tile * GPB + grp;
-    const bool ok = row < q.view.nV;
-    R acc = 0, pi = 0;
-    if (ok) {
-        const int32_t rb = q.view.rowptr[row];
-        acc = row_apply<R, G, KP, false>(q.view.col, q.K, beta, alpha * q.M[row], nullptr, q.p, row,
-                                         rb, q.view.rowptr[row + 1] - rb, q.k, lane, gbase, &pi);
-    }
-    const bool out = ok && lane < q.k && lane < KP;
+    const bool out_lane = lane < q.k && lane < KP;
     double ds = 0.0;
-    if (out) {
-        const int64_t e = (int64_t)row * q.k + lane;
-        q.q[e] = acc;
-        if (G != KP) pi = q.p[e];  // row_apply returns p[i, c] only when G == KP
-        ds = (double)pi * (double)acc;
+    const int32_t tb = unit * kSrvTilesPerUnit, te = min(tb + kSrvTilesPerUnit, q.tiles_s);
+    if (q.ell_w && q.ell_w <= G) {
+        // padded rows, the next tile's entries loaded while this tile's
+        // gathers are in flight
+        const int32_t nV = q.view.nV, W = q.ell_w;
+        int32_t row = tb * GPB + grp, cj;
+        R aj;
+        ell_entry(q.ell_col, q.v, W, row < nV ? row : 0, lane, cj, aj);
+        for (int32_t tile = tb; tile < te; ++tile, row += GPB) {
+            const int32_t cj0 = cj;
+            const R aj0 = aj;
+            if (tile + 1 < te && row + GPB < nV) ell_entry(q.ell_col, q.v, W, row + GPB, lane, cj, aj);
+            if (row >= nV) continue;  // uniform over the lane group
+            R ri = 0;
+            const R acc = ell_row<R, G, KP>(cj0, aj0, q.r, row, q.k, lane, gbase, &ri);
+            if (out_lane) {
+                const int64_t e = (int64_t)row * q.k + lane;
+                q.w[e] = acc;
+                if (G != KP) ri = q.r[e];  // ell_row returns r[i, c] only when G == KP
+                ds += (double)acc * (double)(q.invD[row] * ri);
+            }
+        }
+        column_partials(&ds, 1, q.k, G, out_lane, s_red, s_part);
+        if ((int)threadIdx.x < q.k) q.part2[(size_t)threadIdx.x * q.units_s + unit] = s_part[threadIdx.x];
+        __syncthreads();
+        return;
     }
-    column_partials(&ds, 1, q.k, G, out, s_red, s_part);
-    if ((int)threadIdx.x < q.k) q.part[(size_t)threadIdx.x * q.tiles_s + tile] = s_part[threadIdx.x];
+    for (int32_t tile = tb; tile < te; ++tile) {
+        const int32_t row = tile * GPB + grp;
+        if (row >= q.view.nV) continue;  // uniform over the lane group
+        int32_t rb, len;
+        const int32_t *col;
+        if (q.ell_w) {  // padded rows: no row pointer load
+            rb = row * q.ell_w;
+            len = q.ell_w;
+            col = q.ell_col;
+        } else {
+            rb = q.view.rowptr[row];
+            len = q.view.rowptr[row + 1] - rb;
+            col = q.view.col;
+        }
+        R ri = 0;
+        const R acc = row_apply<R, G, KP, false>(col, q.v, R(1), R(0), nullptr, q.r, row, rb, len,
+                                                 q.k, lane, gbase, &ri);
+        if (out_lane) {
+            const int64_t e = (int64_t)row * q.k + lane;
+            q.w[e] = acc;
+            if (G != KP) ri = q.r[e];  // row_apply returns r[i, c] only when G == KP
+            ds += (double)acc * (double)(q.invD[row] * ri);
+        }
+    }
+    column_partials(&ds, 1, q.k, G, out_lane, s_red, s_part);
+    if ((int)threadIdx.x < q.k) q.part2[(size_t)threadIdx.x * q.units_s + unit] = s_part[threadIdx.x];
     __syncthreads();
 }
 
-// q = A p with the partial sums of p.q, iteration j of the tick.
-__global__ void __launch_bounds__(T)
-ks_spmm(const SrvHdr *hdr, const SrvDesc *d, int j, R alpha, R beta) {
+// w = A D^-1 r with the partial sums of w.z; j < 0: the start of the solve.
+__global__ void __launch_bounds__(T, 6)
+ks_sdot(const SrvHdr *hdr, const SrvDesc *d, int j) {
     __shared__ double s_part[kSrvMaxK];
     __shared__ double s_red[red_scratch(T, 1)];
-    const int n = hdr->n, tot = hdr->tot_s;
-    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
-        const SrvDesc &q = d[find_req(d, n, v, SP_S)];
-        if (j >= q.iters) continue;
-        const int32_t tile = v - q.off_s;
+    for_tiles(d, hdr->n, hdr->tot_s, SP_S, [&](const SrvDesc &q, int32_t unit) {
+        if (j < 0 ? !q.init : j >= q.iters) return;
         switch (q.KP) {
-            case 1: spmm_tile<1>(q, tile, alpha, beta, s_red, s_part); break;
-            case 2: spmm_tile<2>(q, tile, alpha, beta, s_red, s_part); break;
-            case 4: spmm_tile<4>(q, tile, alpha, beta, s_red, s_part); break;
-            case 8: spmm_tile<8>(q, tile, alpha, beta, s_red, s_part); break;
-            default: spmm_tile<16>(q, tile, alpha, beta, s_red, s_part); break;
+            case 1: sdot_unit<1>(q, unit, s_red, s_part); break;
+            case 2: sdot_unit<2>(q, unit, s_red, s_part); break;
+            case 4: sdot_unit<4>(q, unit, s_red, s_part); break;
+            case 8: sdot_unit<8>(q, unit, s_red, s_part); break;
+            default: sdot_unit<16>(q, unit, s_red, s_part); break;
         }
-    }
+    });
 }
 
-// One workgroup per request: reduce its partial sums and advance its state.
+// One workgroup per request: reduce its partial sums and advance its state
+// (FIN_SR_INIT at the start of the solve, FIN_SR_ITER after iteration j).
 template <int MODE>
 __global__ void __launch_bounds__(kFinThreads)
 ks_fin(const SrvHdr *hdr, const SrvDesc *d, int j, CgParams prm) {
-    __shared__ double s_tot[3 * kSrvMaxK];
+    __shared__ double s_tot[4 * kSrvMaxK];
     for (int r = blockIdx.x; r < hdr->n; r += gridDim.x) {
         const SrvDesc &q = d[r];
-        if (MODE == FIN_INIT ? !q.init : j >= q.iters) continue;
-        const int nt = MODE == FIN_ALPHA ? q.tiles_s : q.tiles_v;
-        fin_sum(q.part, nt, fin_width(MODE, q.k), s_tot);
-        if ((int)threadIdx.x < q.k) cg_state_update(MODE, q.st[threadIdx.x], s_tot, threadIdx.x, q.k, prm);
+        if (MODE == FIN_SR_INIT ? !q.init : j >= q.iters) continue;
+        const int W = fin_width(MODE, q.k);
+        fin_sum2(q.part, q.units_v, W, q.part2, q.units_s, q.k, s_tot);
+        if ((int)threadIdx.x < q.k) {
+            CgCol c = MODE == FIN_SR_INIT ? CgCol{} : q.st[threadIdx.x];
+            cg_sr_update(MODE, c, s_tot, s_tot + W, threadIdx.x, q.k, prm);
+            q.st[threadIdx.x] = c;
+        }
         __syncthreads();
     }
 }
 
-// r -= alpha q; partial sums of r.z (z = D^-1 r) and r.r.
+// p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s on the active
+// columns (z = D^-1 r); partial sums of r.z and r.r of the new residual.
 __global__ void __launch_bounds__(T)
-ks_update(const SrvHdr *hdr, const SrvDesc *d, int j) {
+ks_vupdate(const SrvHdr *hdr, const SrvDesc *d, int j) {
     __shared__ double s_part[2 * kSrvMaxK];
     __shared__ double s_red[red_scratch(T, 2)];
-    const int n = hdr->n, tot = hdr->tot_v;
-    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
-        const SrvDesc &q = d[find_req(d, n, v, SP_V)];
-        if (j >= q.iters) continue;
-        const int32_t tile = v - q.off_v;
+    for_tiles(d, hdr->n, hdr->tot_v, SP_V, [&](const SrvDesc &q, int32_t unit) {
+        if (j >= q.iters) return;
         const VLane L = vlane(q.k, q.KP);
-        const int64_t i = (int64_t)tile * L.gpb + L.grp;
-        const bool on = L.act && i < q.view.nV && q.st[L.c].active;
+        const bool on = L.act && q.st[L.c].active;
         double dd[2] = {0.0, 0.0};
         if (on) {
-            const R a = (R)q.st[L.c].alpha;
-            const int64_t e = i * q.k + L.c;
-            const R rv = q.r[e] - a * q.q[e];
-            const R zv = q.invD[i] * rv;
-            q.r[e] = rv;
-            dd[0] = (double)rv * (double)zv;
-            dd[1] = (double)rv * (double)rv;
+            const R a = (R)q.st[L.c].alpha, bt = (R)q.st[L.c].beta;
+            const int32_t tb = unit * kSrvTilesPerUnit, te = min(tb + kSrvTilesPerUnit, q.tiles_v);
+            for (int32_t tile = tb; tile < te; ++tile) {
+                const int64_t i = (int64_t)tile * L.gpb + L.grp;
+                if (i >= q.view.nV) continue;
+                const int64_t e = i * q.k + L.c;
+                const R rv = q.r[e], dv = q.invD[i];
+                const R pn = dv * rv + bt * q.p[e];
+                const R sn = q.w[e] + bt * q.s[e];
+                const R rn = rv - a * sn;
+                q.p[e] = pn;
+                q.s[e] = sn;
+                q.u[e] += a * pn;
+                q.r[e] = rn;
+                const R zn = dv * rn;
+                dd[0] += (double)rn * (double)zn;
+                dd[1] += (double)rn * (double)rn;
+            }
         }
         column_partials(dd, 2, q.k, q.KP, on, s_red, s_part);
         const int W = 2 * q.k;
-        if ((int)threadIdx.x < W) q.part[(size_t)threadIdx.x * q.tiles_v + tile] = s_part[threadIdx.x];
+        if ((int)threadIdx.x < W) q.part[(size_t)threadIdx.x * q.units_v + unit] = s_part[threadIdx.x];
         __syncthreads();
-    }
-}
-
-// x += alpha p; p = D^-1 r + beta p for columns still active.
-__global__ void __launch_bounds__(T)
-ks_pupdate(const SrvHdr *hdr, const SrvDesc *d, int j) {
-    const int n = hdr->n, tot = hdr->tot_v;
-    for (int32_t v = blockIdx.x; v < tot; v += gridDim.x) {
-        const SrvDesc &q = d[find_req(d, n, v, SP_V)];
-        if (j >= q.iters) continue;
-        const int32_t tile = v - q.off_v;
-        const VLane L = vlane(q.k, q.KP);
-        const int64_t i = (int64_t)tile * L.gpb + L.grp;
-        if (!L.act || i >= q.view.nV) continue;
-        const CgCol &s = q.st[L.c];
-        if (s.alpha == 0.0 && !s.active) continue;
-        const int64_t e = i * q.k + L.c;
-        const R pv = q.p[e];
-        q.u[e] += (R)s.alpha * pv;
-        if (s.active) q.p[e] = q.invD[i] * q.r[e] + (R)s.beta * pv;
-    }
+    });
 }
 
 // ------------------------------------------------------------- footprint
@@ -239,24 +322,26 @@ int64_t tiles_for(int32_t nV, int rows) { return ((int64_t)nV + rows - 1) / rows
 int64_t footprint_of(int32_t nV, int64_t nF, int32_t k, bool per_mesh_path) {
     const int64_t nE = 3 * nF, nnz = (int64_t)nV + 2 * nE, V1 = (int64_t)nV + 1;
     const int KP = pow2ceil(k), G = KP < 8 ? 8 : KP;
-    const int64_t tv = tiles_for(nV, T / KP), ts = tiles_for(nV, T / G);
+    const int64_t tv = (tiles_for(nV, T / KP) + kSrvTilesPerUnit - 1) / kSrvTilesPerUnit;
+    const int64_t ts = (tiles_for(nV, T / G) + kSrvTilesPerUnit - 1) / kSrvTilesPerUnit;
     int64_t b = 0;
     b += rnd(12 * nF) + rnd(12 * (int64_t)nV) + rnd(4 * (int64_t)nV * k);  // F, X, f
     // topology construction
     b += rnd(12 * nF) + rnd(32) + 5 * rnd(4 * V1) + rnd(4 * (V1 / 1000 + 64)) + rnd(8 * 3 * nF);
     b += rnd(8 * nE) + rnd(12 * nF) + rnd(3 * nF) + rnd(4 * V1) + rnd(4 * nnz) + rnd(4 * (int64_t)nV) +
          rnd(4 * V1) + rnd(12 * nF) + rnd(nV) + rnd(12 * nF) + rnd(4 * nE);
-    // solver arrays
-    b += rnd(4 * nnz) + rnd(4 * (int64_t)nV) + 4 * rnd(4 * (int64_t)nV * k) + rnd(4 * (int64_t)nV);
-    b += rnd(8 * std::max<int64_t>(3 * k * tv, k * ts)) + rnd((int64_t)sizeof(CgCol) * k);
+    // solver arrays: K, M, u r p s w, D^-1, v, the two partial-sum arrays, state
+    b += rnd(4 * nnz) + rnd(4 * (int64_t)nV) + 5 * rnd(4 * (int64_t)nV * k) + rnd(4 * (int64_t)nV);
+    b += rnd(4 * std::max<int64_t>(nnz, (int64_t)kEllMaxWidth * nV)) + rnd(8 * 3 * k * tv) +
+         rnd(8 * k * ts) + rnd((int64_t)sizeof(CgCol) * k);
+    // row descriptors and the padded-row pattern (natural order)
+    b += rnd(8 * (int64_t)nV) + rnd(nV) + 2 * rnd(4 * (int64_t)kEllMaxWidth * nV);
     if (per_mesh_path) {
         // the per-mesh PCG workspace (grown once, with headroom) and the
         // assembly counter
         const int64_t nvals = std::max<int64_t>(nnz, (int64_t)kEllMaxWidth * nV);
         const int64_t ws = (int64_t)pcg_layout(nV, nvals, k, sizeof(float)).total;
         b += rnd(ws + ws / 4) + rnd(320);
-        // SpMV row descriptors and the padded-row pattern
-        b += rnd(8 * (int64_t)nV) + rnd(nV) + 2 * rnd(4 * (int64_t)kEllMaxWidth * nV);
     }
     return b + 8192;
 }
@@ -293,6 +378,7 @@ class GpuExec {
         DGO_HIP(hipGetDevice(&dev_));
         DGO_HIP(hipMalloc(&arena_, (size_t)o_.hbm_budget_bytes));
         DGO_HIP(hipStreamCreateWithFlags(&cs_, hipStreamNonBlocking));
+        DGO_HIP(hipStreamCreateWithFlags(&xs_, hipStreamNonBlocking));
         const size_t db = sizeof(SrvHdr) + sizeof(SrvDesc) * kSrvMaxSlots;
         DGO_HIP(hipHostMalloc(&h_desc_, db, hipHostMallocDefault));
         DGO_HIP(hipMalloc(&d_desc_, db));
@@ -305,6 +391,7 @@ class GpuExec {
         if (graph_) (void)hipGraphExecDestroy(graph_);
         for (auto &kv : prep_streams_) (void)hipStreamDestroy(kv.second);
         if (cs_) (void)hipStreamDestroy(cs_);
+        if (xs_) (void)hipStreamDestroy(xs_);
         if (h_desc_) (void)hipHostFree(h_desc_);
         if (d_desc_) (void)hipFree(d_desc_);
         if (d_ndeg_) (void)hipFree(d_ndeg_);
@@ -337,13 +424,16 @@ class GpuExec {
         // the batched kernels read the CSR directly; the one-at-a-time
         // baseline goes through the SpMV entry points, which need row
         // descriptors (natural order: no host-side reordering per request)
-        dgo_status st = mesh_create(2, in.nV, in.nF, dF, &al, ps,
-                                    o_.batched ? ROWS_NONE : ROWS_NATURAL, &rd->mesh);
+        dgo_status st = mesh_create(2, in.nV, in.nF, dF, &al, ps, ROWS_NATURAL,
+                                    o_.batched ? kSrvLdsBytes : 0, &rd->mesh);
         if (st != DGO_OK) return st;
         dgo_mesh *m = rd->mesh;
         SrvDesc &D = rd->desc;
         D.view = view_of(m);
         D.diag = m->diag;
+        D.ell_col = m->ell_col;
+        D.ell_src = m->ell_src;
+        D.ell_w = m->ell_w;
         D.nnz = m->nnz;
         D.X = dX;
         D.f = df;
@@ -352,17 +442,23 @@ class GpuExec {
         const int G = D.KP < 8 ? 8 : D.KP;
         D.tiles_v = (int32_t)tiles_for(in.nV, T / D.KP);
         D.tiles_s = (int32_t)tiles_for(in.nV, T / G);
+        D.units_v = (D.tiles_v + kSrvTilesPerUnit - 1) / kSrvTilesPerUnit;
+        D.units_s = (D.tiles_s + kSrvTilesPerUnit - 1) / kSrvTilesPerUnit;
         D.nblocks = m->nblocks;
         D.K = (R *)take(4 * m->nnz);
         D.M = (R *)take(4 * nV);
         D.u = (R *)take(4 * nV * k);
         D.r = (R *)take(4 * nV * k);
         D.p = (R *)take(4 * nV * k);
-        D.q = (R *)take(4 * nV * k);
+        D.s = (R *)take(4 * nV * k);
+        D.w = (R *)take(4 * nV * k);
         D.invD = (R *)take(4 * nV);
-        D.part = (double *)take(8 * std::max<int64_t>(3 * k * D.tiles_v, k * D.tiles_s));
+        D.v = (R *)take(4 * (m->ell_w ? (int64_t)m->ell_w * nV : m->nnz));
+        D.part = (double *)take(8 * 3 * k * (int64_t)D.units_v);
+        D.part2 = (double *)take(8 * k * (int64_t)D.units_s);
         D.st = (CgCol *)take((int64_t)sizeof(CgCol) * k);
-        if (!D.K || !D.M || !D.u || !D.r || !D.p || !D.q || !D.invD || !D.part || !D.st)
+        if (!D.K || !D.M || !D.u || !D.r || !D.p || !D.s || !D.w || !D.invD || !D.v || !D.part ||
+            !D.part2 || !D.st)
             return DGO_ERR_NOMEM;
         DGO_HIP(hipStreamSynchronize(ps));
         return DGO_OK;
@@ -385,8 +481,8 @@ class GpuExec {
             D.off_s = os;
             D.off_v = ov;
             oa += D.init ? D.nblocks : 0;
-            os += D.tiles_s;
-            ov += D.tiles_v;
+            os += D.units_s;
+            ov += D.units_v;
             hd[i] = D;
         }
         *h = SrvHdr{n, oa, os, ov};
@@ -419,12 +515,14 @@ class GpuExec {
         return DGO_OK;
     }
 
+    // On the completion thread, after the tick that finished the request has
+    // completed; its own stream lets the copy overlap the next tick.
     dgo_status finish(srv::Req &q) {
         ReqDev *rd = (ReqDev *)q.exec;
         (void)hipSetDevice(dev_);
         DGO_HIP(hipMemcpyAsync(q.in.h_u, rd->desc.u, 4 * (size_t)q.in.nV * q.in.k,
-                               hipMemcpyDeviceToHost, cs_));
-        DGO_HIP(hipStreamSynchronize(cs_));
+                               hipMemcpyDeviceToHost, xs_));
+        DGO_HIP(hipStreamSynchronize(xs_));
         return DGO_OK;
     }
 
@@ -461,15 +559,15 @@ class GpuExec {
         prm.k = 0;
         const unsigned nfin = (unsigned)std::min(o_.max_slots, kSrvMaxSlots);
         DGO_LAUNCH("srv_assemble", cs_,
-                   ks_assemble<<<kSrvAsmBlocks, kAssembleThreads, kRowBlockLdsBytes, cs_>>>(hd, dd, d_ndeg_));
+                   ks_assemble<<<kSrvAsmBlocks, kAssembleThreads, kSrvLdsBytes, cs_>>>(hd, dd, d_ndeg_));
         DGO_LAUNCH("srv_init", cs_, ks_init<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, a, b));
-        DGO_LAUNCH("srv_fin", cs_, ks_fin<FIN_INIT><<<nfin, kFinThreads, 0, cs_>>>(hd, dd, 0, prm));
+        DGO_LAUNCH("srv_values", cs_, ks_values<<<kSrvAsmBlocks, T, 0, cs_>>>(hd, dd, a, b));
+        DGO_LAUNCH("srv_sdot", cs_, ks_sdot<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, -1));
+        DGO_LAUNCH("srv_fin", cs_, ks_fin<FIN_SR_INIT><<<nfin, kFinThreads, 0, cs_>>>(hd, dd, 0, prm));
         for (int j = 0; j < chunk; ++j) {
-            DGO_LAUNCH("srv_spmm", cs_, ks_spmm<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, j, a, b));
-            DGO_LAUNCH("srv_fin", cs_, ks_fin<FIN_ALPHA><<<nfin, kFinThreads, 0, cs_>>>(hd, dd, j, prm));
-            DGO_LAUNCH("srv_update", cs_, ks_update<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, j));
-            DGO_LAUNCH("srv_fin", cs_, ks_fin<FIN_BETA><<<nfin, kFinThreads, 0, cs_>>>(hd, dd, j, prm));
-            DGO_LAUNCH("srv_pupdate", cs_, ks_pupdate<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, j));
+            DGO_LAUNCH("srv_vupdate", cs_, ks_vupdate<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, j));
+            DGO_LAUNCH("srv_sdot", cs_, ks_sdot<<<kSrvBlocks, T, 0, cs_>>>(hd, dd, j));
+            DGO_LAUNCH("srv_fin", cs_, ks_fin<FIN_SR_ITER><<<nfin, kFinThreads, 0, cs_>>>(hd, dd, j, prm));
         }
     }
 
@@ -498,7 +596,7 @@ class GpuExec {
     int dev_ = 0;
     void *arena_ = nullptr, *h_desc_ = nullptr, *d_desc_ = nullptr;
     int32_t *d_ndeg_ = nullptr;
-    hipStream_t cs_ = nullptr;
+    hipStream_t cs_ = nullptr, xs_ = nullptr;  // ticks; result copies
     hipGraphExec_t graph_ = nullptr;
     int32_t graph_chunk_ = -1;
     std::mutex mu_;

@@ -484,6 +484,7 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
     // row blocks: the most rows per workgroup whose CSR span and incidence
     // records fit the LDS budget of the assembly kernels
     int32_t rpb = dim == 2 ? kRowsPerBlockTri : kRowsPerBlockTet;
+    const int64_t budget = m->lds_budget > 0 ? m->lds_budget : kRowBlockLdsBytes;
     for (;;) {
         DGO_HIP(hipMemsetAsync(flags + 5, 0, 2 * sizeof(int32_t), s));
         int32_t nb = (int32_t)((nV + rpb - 1) / rpb);
@@ -491,7 +492,7 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
         DGO_HIP(hipGetLastError());
         DGO_HIP(hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s));
         DGO_HIP(hipStreamSynchronize(s));
-        if (assembly_lds_bytes(dim, 8, rpb, hf[5], hf[6]) <= kRowBlockLdsBytes || rpb <= 1) break;
+        if (assembly_lds_bytes(dim, 8, rpb, hf[5], hf[6]) <= budget || rpb <= 1) break;
         rpb /= 2;
     }
     m->n_bfaces = hf[2];
@@ -503,7 +504,7 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
     m->max_block_inc = hf[6];
     if (m->max_row > 255)
         return fail(DGO_ERR_UNSUPPORTED, "mesh: a vertex has more than 254 neighbours");
-    if (assembly_lds_bytes(dim, 8, rpb, hf[5], hf[6]) > kRowBlockLdsBytes)
+    if (assembly_lds_bytes(dim, 8, rpb, hf[5], hf[6]) > budget)
         return fail(DGO_ERR_UNSUPPORTED, "mesh: a vertex's row exceeds the LDS budget");
     return DGO_OK;
 }
@@ -629,7 +630,7 @@ using namespace dgo;
 
 dgo_status dgo::mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_t *d_elem,
                             const dgo_allocator *alloc, hipStream_t s, RowsMode rows,
-                            dgo_mesh **out) {
+                            int64_t lds_budget, dgo_mesh **out) {
     clear_error();
     if (!out) return fail(DGO_ERR_INVALID_ARG, "dgo_mesh_create: out is NULL");
     *out = nullptr;
@@ -652,6 +653,7 @@ dgo_status dgo::mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32
         m->alloc.has_user = true;
     }
     m->home = s;
+    m->lds_budget = lds_budget;
     (void)hipGetDevice(&m->device);
     dgo_status st = build(m, d_elem, s);
     if (st == DGO_OK && rows != ROWS_NONE) st = build_row_desc(m, s, rows == ROWS_AUTO);
@@ -671,7 +673,7 @@ dgo_status dgo::mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32
 extern "C" dgo_status dgo_mesh_create(int32_t dim, int32_t nV, int64_t n_elem,
                                       const int32_t *d_elem, const dgo_allocator *alloc,
                                       dgo_stream stream, dgo_mesh **out) {
-    return mesh_create(dim, nV, n_elem, d_elem, alloc, (hipStream_t)stream, ROWS_AUTO, out);
+    return mesh_create(dim, nV, n_elem, d_elem, alloc, (hipStream_t)stream, ROWS_AUTO, 0, out);
 }
 
 extern "C" void dgo_mesh_destroy(dgo_mesh *m) {

@@ -17,9 +17,23 @@ from paper_2602_12105_amd.serve import Server, footprint  # noqa: E402
 ITERS = 50
 
 
+def _fan(n, seed):
+    """A disk fan: centre 0 joined to a ring of n vertices (a row of n + 1
+    entries, so the server runs it over CSR rows instead of padded rows)."""
+    rng = np.random.default_rng(seed)
+    th = np.linspace(0, 2 * np.pi, n, endpoint=False)
+    X = np.zeros((n + 1, 3))
+    X[1:, 0], X[1:, 1] = np.cos(th), np.sin(th)
+    X[1:, 2] = 0.05 * rng.standard_normal(n)
+    F = np.array([[0, 1 + i, 1 + (i + 1) % n] for i in range(n)], np.int32)
+    return X, F
+
+
 def _request(kind, size, k, seed):
     if kind == "grid":
         X, F = meshgen.grid2d(size, 0.2, seed)
+    elif kind == "fan":
+        X, F = _fan(size, seed)
     else:
         X, F = meshgen.icosphere(size, 1e-3, seed)
     f = meshgen.normal(seed + 7, X.shape[0] * k).reshape(-1, k)
@@ -35,7 +49,7 @@ def _oracle(F, X, f, iters=ITERS):
 
 
 MIX = [("grid", 12, 1), ("ico", 3, 8), ("grid", 31, 16), ("ico", 2, 3), ("grid", 7, 5),
-       ("ico", 4, 12), ("grid", 20, 2), ("ico", 1, 16)]
+       ("ico", 4, 12), ("grid", 20, 2), ("ico", 1, 16), ("fan", 40, 4)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -58,7 +72,7 @@ def test_batched_matches_oracle_and_is_mix_independent():
         err = np.abs(u.astype(np.float64) - ref).max() / np.abs(ref).max()
         assert err <= 1e-4, err
     # alone: the same request on an otherwise empty server gives the same bits
-    for i in (2, 5):
+    for i in (2, 5, 8):
         F, X, f = reqs[i]
         with Server(hbm_budget_bytes=1 << 30, max_slots=16, cg_iters=ITERS, cg_chunk=10) as s:
             alone = s.wait(s.submit(F, X, f))[0]
