@@ -469,7 +469,7 @@ def _run_server(dgo_serve, pool, n_req, rate, batched, seed):
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, n_req) if rate else np.zeros(n_req)
     srv = dgo_serve.Server(hbm_budget_bytes=32 << 30, max_slots=128 if batched else 1,
-                           cg_iters=50, cg_chunk=10, batched=batched, prep_threads=8)
+                           cg_iters=50, cg_chunk=10, batched=batched, prep_threads=4)
     tickets = [None] * n_req
     submitted = threading.Event()
     lat, starts, ends = [], [], []

@@ -131,6 +131,163 @@ k_assemble_vjp_tri(const int32_t *__restrict__ rowptr, const int32_t *__restrict
     gX[3 * (int64_t)i + 2] = g.z;
 }
 
+// Topology of the row-block VJP, built on the mesh's first VJP call: for each
+// CSR slot (i, j) the slot of (j, i) and the diagonal slot of column j; for
+// each incidence (vertex i, triangle (i, a, b)) the slots of (a, b) and (b, a).
+__global__ void k_vjp_topo(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                           const int32_t *__restrict__ diag, const int32_t *__restrict__ vtptr,
+                           const uint32_t *__restrict__ inc, int32_t nV, int32_t *__restrict__ mirror,
+                           int32_t *__restrict__ coldiag, int32_t *__restrict__ opp) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= nV) return;
+    const int32_t rb = rowptr[i], re = rowptr[i + 1];
+    for (int32_t t = rb; t < re; ++t) {
+        const int32_t j = col[t];
+        mirror[t] = find_slot(rowptr, col, j, i);
+        coldiag[t] = diag[j];
+    }
+    for (int32_t q = vtptr[i]; q < vtptr[i + 1]; ++q) {
+        const uint32_t rec = inc[q];
+        const int32_t a = col[rb + (int32_t)(rec & 255u)], b = col[rb + (int32_t)((rec >> 8) & 255u)];
+        opp[2 * (int64_t)q] = find_slot(rowptr, col, a, b);
+        opp[2 * (int64_t)q + 1] = find_slot(rowptr, col, b, a);
+    }
+}
+
+// LDS of the row-block VJP for one block of rows [r0, r1):
+//   cw   : R[3][inc_max]   per-incidence gradient contributions (phase A)
+//   lgd  : R[span_max]     gK at the diagonal of each entry's column
+//   lsum : R[span_max]     gK_ij + gK_ji of each entry
+//   lgm  : R[span_max]     gM of each entry's column
+//   xo   : R[3][rpb]       the block's own positions
+//   lgii : R[rpb], lgmi : R[rpb]   gK_ii and gM_i of the block's rows
+//   lcol : int32[span_max], lrec : uint32[inc_max], lopp : int32[2][inc_max],
+//   lrp, lvt : int32[rpb + 1]
+inline int64_t vjp_lds_bytes(int s, int64_t rpb, int64_t span, int64_t ninc) {
+    return ninc * (3 * s + 12) + span * (3 * s + 4) + rpb * 5 * s + 2 * (rpb + 1) * 4 + 64;
+}
+
+// Row-block VJP: the block stages its rows' CSR span, incidence records and
+// the gK, gM values they need in LDS (coalesced); phase A runs one thread per
+// (vertex, triangle) incidence and forms the triangle's contribution to that
+// vertex's gradient (the same terms, in the same order, as the per-row form
+// above); phase B runs one thread per row and adds them in element order.
+// The only gathers are the two other positions and gK of the opposite edge.
+template <typename R>
+__global__ void __launch_bounds__(kAssembleThreads)
+k_vjp_rows(AsmView v, const int32_t *__restrict__ diag, const int32_t *__restrict__ mirror,
+           const int32_t *__restrict__ coldiag, const int32_t *__restrict__ opp, int32_t nblocks,
+           int64_t nnz, const R *__restrict__ X, const R *__restrict__ gK,
+           const R *__restrict__ gM, R *__restrict__ gX) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int32_t nV = v.nV, rpb = v.rpb, span_max = v.span_max, inc_max = v.inc_max;
+    const int64_t bt = blockIdx.y;
+    X += bt * 3 * (int64_t)nV;
+    gX += bt * 3 * (int64_t)nV;
+    if (gK) gK += bt * nnz;
+    if (gM) gM += bt * (int64_t)nV;
+    R *cw = (R *)smem;
+    R *lgd = cw + 3 * (size_t)inc_max;
+    R *lsum = lgd + span_max;
+    R *lgm = lsum + span_max;
+    R *xo = lgm + span_max;
+    R *lgii = xo + 3 * (size_t)rpb;
+    R *lgmi = lgii + rpb;
+    int32_t *lcol = (int32_t *)(lgmi + rpb);
+    uint32_t *lrec = (uint32_t *)(lcol + span_max);
+    int32_t *lopp = (int32_t *)(lrec + inc_max);
+    int32_t *lrp = lopp + 2 * (size_t)inc_max;
+    int32_t *lvt = lrp + rpb + 1;
+
+    const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)nblocks);
+    const int32_t r0 = (int32_t)tile * rpb;
+    const int32_t r1 = min(r0 + rpb, nV), nrows = r1 - r0;
+    const int32_t s0 = v.rowptr[r0], span = v.rowptr[r1] - s0;
+    const int32_t q0 = v.vtptr[r0], ninc = v.vtptr[r1] - q0;
+    const int t = threadIdx.x;
+    for (int32_t j = t; j <= nrows; j += blockDim.x) {
+        lrp[j] = v.rowptr[r0 + j] - s0;
+        lvt[j] = v.vtptr[r0 + j] - q0;
+    }
+    for (int32_t j = t; j < 3 * nrows; j += blockDim.x) {
+        const int32_t r = j / 3, c = j - 3 * r;
+        xo[c * rpb + r] = X[3 * (int64_t)r0 + j];
+    }
+    for (int32_t j = t; j < nrows; j += blockDim.x) {
+        lgii[j] = gK ? gK[diag[r0 + j]] : R(0);
+        lgmi[j] = gM ? gM[r0 + j] : R(0);
+    }
+    for (int32_t j = t; j < span; j += blockDim.x) {
+        const int32_t e = s0 + j, c = v.col[e];
+        lcol[j] = c;
+        lsum[j] = gK ? gK[e] + gK[mirror[e]] : R(0);
+        lgd[j] = gK ? gK[coldiag[e]] : R(0);
+        lgm[j] = gM ? gM[c] : R(0);
+    }
+    for (int32_t q = t; q < ninc; q += blockDim.x) {
+        lrec[q] = v.inc[q0 + q];
+        lopp[q] = opp[2 * (int64_t)(q0 + q)];
+        lopp[inc_max + q] = opp[2 * (int64_t)(q0 + q) + 1];
+    }
+    __syncthreads();
+    for (int32_t q = t; q < ninc; q += blockDim.x) {
+        const uint32_t rec = lrec[q];
+        const int32_t rr = row_of(lvt, nrows, q);
+        const int32_t base = lrp[rr];
+        const int32_t la = base + (int32_t)(rec & 255u), lb = base + (int32_t)((rec >> 8) & 255u);
+        const int32_t a = lcol[la], b = lcol[lb];
+        const V3<R> xi = {xo[rr], xo[rpb + rr], xo[2 * rpb + rr]};
+        const V3<R> xa = ld3(X, a), xb = ld3(X, b);
+        // weight gradients: w_pq enters K_pq, K_qp with -1 and K_pp, K_qq with +1
+        R gia = 0, gib = 0, gab = 0;
+        if (gK) {
+            gia = lgii[rr] + lgd[la] - lsum[la];
+            gib = lgii[rr] + lgd[lb] - lsum[lb];
+            gab = lgd[la] + lgd[lb] - gK[lopp[q]] - gK[lopp[inc_max + q]];
+        }
+        V3<R> g = {R(0), R(0), R(0)};
+        // 1/2 cot(at b) on edge ia: e1 = xi - xb, e2 = xa - xb; d/dxi = d/de1
+        const CotD<R> cb = cot_diff(sub(xi, xb), sub(xa, xb));
+        g = axpy(R(0.5) * gia, cb.d1, g);
+        // 1/2 cot(at a) on edge ib: e1 = xi - xa, e2 = xb - xa
+        const CotD<R> ca = cot_diff(sub(xi, xa), sub(xb, xa));
+        g = axpy(R(0.5) * gib, ca.d1, g);
+        // 1/2 cot(at i) on edge ab: e1 = xa - xi, e2 = xb - xi; d/dxi = -(d1 + d2)
+        const CotD<R> ci = cot_diff(sub(xa, xi), sub(xb, xi));
+        const R hi = R(-0.5) * gab;
+        g = axpy(hi, ci.d1, g);
+        g = axpy(hi, ci.d2, g);
+        if (gM) {
+            // d area/dxi = -[(|e2|^2 e1 - d e2) + (|e1|^2 e2 - d e1)] / (2 s)
+            const V3<R> e1 = sub(xa, xi), e2 = sub(xb, xi);
+            const V3<R> n = cross(e1, e2);
+            const R sn = sqrt(dot(n, n));
+            const R d = dot(e1, e2), l1 = dot(e1, e1), l2 = dot(e2, e2);
+            const R ga = -(lgmi[rr] + lgm[la] + lgm[lb]) / R(3) / (R(2) * sn);
+            g = axpy(ga, V3<R>{l2 * e1.x - d * e2.x + l1 * e2.x - d * e1.x,
+                               l2 * e1.y - d * e2.y + l1 * e2.y - d * e1.y,
+                               l2 * e1.z - d * e2.z + l1 * e2.z - d * e1.z},
+                     g);
+        }
+        cw[q] = g.x;
+        cw[inc_max + q] = g.y;
+        cw[2 * (size_t)inc_max + q] = g.z;
+    }
+    __syncthreads();
+    for (int32_t rr = t; rr < nrows; rr += blockDim.x) {
+        R gx = 0, gy = 0, gz = 0;
+        for (int32_t q = lvt[rr]; q < lvt[rr + 1]; ++q) {
+            gx += cw[q];
+            gy += cw[inc_max + q];
+            gz += cw[2 * (size_t)inc_max + q];
+        }
+        const int64_t o = 3 * (int64_t)(r0 + rr);
+        gX[o] = gx;
+        gX[o + 1] = gy;
+        gX[o + 2] = gz;
+    }
+}
+
 __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
 template <typename R>
@@ -195,6 +352,39 @@ extern "C" dgo_status dgo_assemble_vjp(const dgo_mesh *m, dgo_dtype dtype, int32
     if (dtype != DGO_F32 && dtype != DGO_F64) return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_vjp: bad dtype");
     if (batch < 1 || batch > 65535) return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_vjp: bad batch");
     hipStream_t s = (hipStream_t)stream;
+    const int es = dtype == DGO_F64 ? 8 : 4;
+    const int64_t lds = vjp_lds_bytes(es, m->rpb, m->max_block_nnz, m->max_block_inc);
+    if (lds <= kRowBlockLdsBytes) {
+        dgo_mesh *mm = const_cast<dgo_mesh *>(m);
+        if (!mm->vjp_mirror) {
+            mm->vjp_mirror = (int32_t *)mm->alloc.get(sizeof(int32_t) * (size_t)m->nnz, s);
+            mm->vjp_coldiag = (int32_t *)mm->alloc.get(sizeof(int32_t) * (size_t)m->nnz, s);
+            mm->vjp_opp = (int32_t *)mm->alloc.get(sizeof(int32_t) * 2 * (size_t)m->n_inc, s);
+            if (!mm->vjp_mirror || !mm->vjp_coldiag || !mm->vjp_opp)
+                return fail(DGO_ERR_NOMEM, "dgo_assemble_vjp: topology allocation failed");
+            DGO_LAUNCH("vjp_topo", s,
+                       k_vjp_topo<<<grid_for(m->nV, T), T, 0, s>>>(m->rowptr, m->col, m->diag,
+                                                                   m->vtptr, m->inc, m->nV,
+                                                                   mm->vjp_mirror, mm->vjp_coldiag,
+                                                                   mm->vjp_opp));
+        }
+        dim3 grid((unsigned)m->nblocks, (unsigned)batch);
+        if (dtype == DGO_F64)
+            DGO_LAUNCH("assemble_vjp_tri", s,
+                       k_vjp_rows<double><<<grid, kAssembleThreads, (size_t)lds, s>>>(
+                           view_of(m), m->diag, m->vjp_mirror, m->vjp_coldiag, m->vjp_opp,
+                           m->nblocks, m->nnz, (const double *)d_X, (const double *)d_gK,
+                           (const double *)d_gM, (double *)d_gX));
+        else
+            DGO_LAUNCH("assemble_vjp_tri", s,
+                       k_vjp_rows<float><<<grid, kAssembleThreads, (size_t)lds, s>>>(
+                           view_of(m), m->diag, m->vjp_mirror, m->vjp_coldiag, m->vjp_opp,
+                           m->nblocks, m->nnz, (const float *)d_X, (const float *)d_gK,
+                           (const float *)d_gM, (float *)d_gX));
+        DGO_HIP(hipGetLastError());
+        return DGO_OK;
+    }
+    // rows too long for the row-block form: one thread per row
     int32_t nb = (int32_t)grid_for(m->nV, T);
     dim3 grid((unsigned)nb, (unsigned)batch);
     if (dtype == DGO_F64)

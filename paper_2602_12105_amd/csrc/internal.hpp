@@ -110,6 +110,12 @@ struct dgo_mesh {
     int32_t ell_w = 0;
     int32_t *ell_col = nullptr;    // nV x ell_w
     int32_t *ell_src = nullptr;    // nV x ell_w
+    // topology of the row-block VJP (built on its first call): per CSR slot
+    // (i, j) the slot of (j, i) and the diagonal slot of column j; per
+    // incidence (i, triangle (i, a, b)) the slots of (a, b) and (b, a)
+    int32_t *vjp_mirror = nullptr;   // nnz
+    int32_t *vjp_coldiag = nullptr;  // nnz
+    int32_t *vjp_opp = nullptr;      // 2 x n_inc
 
     // row blocks for the row-centric kernels
     int32_t rpb = 0;            // rows per workgroup

@@ -620,7 +620,8 @@ static void release(dgo_mesh *m, hipStream_t s) {
     m->poll_host = nullptr;
     void *ptrs[] = {m->elem, m->EV, m->elem_edge, m->elem_sign, m->rowptr, m->col,
                     m->diag, m->vtptr, m->inc, m->bmask, m->rdesc, m->rlen, m->order,
-                    m->ell_col, m->ell_src, m->ws};
+                    m->ell_col, m->ell_src, m->vjp_mirror, m->vjp_coldiag, m->vjp_opp,
+                    m->ws};
     for (void *p : ptrs) m->alloc.put(p, s);
 }
 

@@ -311,6 +311,41 @@ def test_vjp_parity(dtype):
     assert np.abs(gX - ref).max() <= tol * np.abs(ref).max()
 
 
+def _fans(n_fans, spokes, seed):
+    """n_fans disjoint disk fans with their centres numbered 0 .. n_fans - 1:
+    the first row blocks hold many rows of spokes + 1 entries."""
+    rng = np.random.default_rng(seed)
+    th = np.linspace(0, 2 * np.pi, spokes, endpoint=False)
+    X = np.zeros((n_fans * (spokes + 1), 3))
+    F = []
+    for f in range(n_fans):
+        X[f] = (3.0 * f, 0.0, 0.0)
+        ring = n_fans + f * spokes
+        X[ring:ring + spokes, 0] = 3.0 * f + np.cos(th)
+        X[ring:ring + spokes, 1] = np.sin(th)
+        X[ring:ring + spokes, 2] = 0.05 * rng.standard_normal(spokes)
+        F += [[f, ring + k, ring + (k + 1) % spokes] for k in range(spokes)]
+    return X, np.array(F, np.int32)
+
+
+@pytest.mark.parametrize("shape", ["ico4", "fans"])
+def test_vjp_row_block_and_long_rows(shape):
+    """The row-block VJP (ico4) and the per-row form it falls back to when a
+    row block of very long rows does not fit its LDS budget (fans)."""
+    print(f"[vjp] {shape}", flush=True)
+    X, F = meshgen.icosphere(4, 1e-2, 5) if shape == "ico4" else _fans(64, 150, 5)
+    m = dgo.Mesh(torch.from_numpy(F).to(DEV), X.shape[0])
+    Xd = torch.from_numpy(X).to(DEV)
+    gK = torch.from_numpy(meshgen.normal(13, m.nnz)).to(DEV)
+    gM = torch.from_numpy(meshgen.normal(14, m.nV)).to(DEV)
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    for a, b in ((gK, gM), (gK, None), (None, gM)):
+        gX = dgo.assemble_vjp(m, Xd, a, b).cpu().numpy()
+        ref = oracle.assemble_vjp_tri(X, F, rp, col, None if a is None else a.cpu().numpy(),
+                                      None if b is None else b.cpu().numpy())
+        assert np.abs(gX - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_autograd_loss_gradient_cfg5():
     """loss = u^T K(x) u + total area through AssembleFn matches the oracle gradient."""
     print("[autograd] batch of icosphere L5", flush=True)
