@@ -54,6 +54,7 @@ def lib():
             "orc_loss_grad_tri": [i32, i64, P, P, P, P, P],
             "orc_loss_cstep_tri": [i32, i64, P, P, P, i32, i32, f64, P],
             "orc_assemble_vjp_tri": [i32, i64, P, P, P, P, P, P, P],
+            "orc_linear_solve_vjp": [i32, P, P, f64, f64, i32, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -215,3 +216,39 @@ def assemble_vjp_tri(X, F, rowptr, col, gK=None, gM=None):
                                       _p(None if gM is None else _f64(gM)), _p(gX)),
            "assemble_vjp_tri")
     return gX
+
+
+def linear_solve_vjp(rowptr, col, alpha, beta, lam, u, f=None):
+    """-> (gK (nnz,), gM (nV,)) of a solve (alpha M + beta K) u = b (b = M f when f is given)."""
+    rowptr, col = _i32(rowptr), _i32(col)
+    nV = rowptr.size - 1
+    lam, u = _f64(lam).reshape(nV, -1), _f64(u).reshape(nV, -1)
+    k = lam.shape[1]
+    f = None if f is None else _f64(f).reshape(nV, k)
+    gK = np.empty(int(rowptr[-1]))
+    gM = np.empty(nV)
+    _check(lib().orc_linear_solve_vjp(nV, _p(rowptr), _p(col), float(alpha), float(beta), k,
+                                      _p(lam), _p(u), _p(f), _p(gK), _p(gM)), "linear_solve_vjp")
+    return gK, gM
+
+
+def mcf_step(X, F, tau, rtol=1e-14, max_iter=20000):
+    """One implicit mean-curvature-flow step (Sec. 7.1) with the PSD stiffness:
+    u = (M + tau K)^{-1} M X, K and M assembled from X. -> (u, K, M, rowptr, col)."""
+    K, M, rp, col = assemble(X, F)
+    b = M[:, None] * _f64(X)
+    u, _, _ = pcg(rp, col, 1.0, M, tau, K, b, rtol=rtol, max_iter=max_iter)
+    return u, K, M, rp, col
+
+
+def mcf_step_grad(X, F, tau, W, rtol=1e-14, max_iter=20000):
+    """Gradient of l = sum(W * u) over one MCF step with respect to X, by the
+    adjoint method: lambda solves the same system with W on the right-hand
+    side; X enters through K(X), M(X) (assembly VJP) and through b = M X
+    (the term M lambda). -> (l, gX)."""
+    X = _f64(X)
+    u, K, M, rp, col = mcf_step(X, F, tau, rtol, max_iter)
+    lam, _, _ = pcg(rp, col, 1.0, M, tau, K, _f64(W), rtol=rtol, max_iter=max_iter)
+    gK, gM = linear_solve_vjp(rp, col, 1.0, tau, lam, u, X)
+    gX = assemble_vjp_tri(X, F, rp, col, gK, gM) + M[:, None] * lam
+    return float(np.sum(_f64(W) * u)), gX

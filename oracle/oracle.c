@@ -661,3 +661,31 @@ int orc_assemble_vjp_tri(int32_t nV, int64_t nF, const int32_t *F, const double 
     }
     return ORC_OK;
 }
+
+/* dl/dA = -lambda u^T restricted to the pattern, split into its K and M parts
+ * (A = alpha M + beta K), plus the right-hand side's dependence on M when
+ * b = M f: db/dM_ii = f_i, so gM_i gains lambda_i . f_i. */
+int orc_linear_solve_vjp(int32_t nV, const int32_t *rowptr, const int32_t *col, double alpha,
+                         double beta, int32_t k, const double *lambda, const double *u,
+                         const double *f, double *gK, double *gM) {
+    if (nV < 1 || k < 1 || !rowptr || !col || !lambda || !u || !gK || !gM)
+        return ORC_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < nV; ++i) {
+        for (int32_t t = rowptr[i]; t < rowptr[i + 1]; ++t) {
+            const int32_t j = col[t];
+            double s = 0.0;
+            for (int32_t c = 0; c < k; ++c) s += lambda[(int64_t)i * k + c] * u[(int64_t)j * k + c];
+            gK[t] = -beta * s;
+        }
+        double m = 0.0;
+        for (int32_t c = 0; c < k; ++c) m += lambda[(int64_t)i * k + c] * u[(int64_t)i * k + c];
+        double g = -alpha * m;
+        if (f) {
+            double q = 0.0;
+            for (int32_t c = 0; c < k; ++c) q += lambda[(int64_t)i * k + c] * f[(int64_t)i * k + c];
+            g += q;
+        }
+        gM[i] = g;
+    }
+    return ORC_OK;
+}

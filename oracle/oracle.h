@@ -97,4 +97,19 @@ int orc_assemble_vjp_tri(int32_t nV, int64_t nF, const int32_t *F, const double 
                          const int32_t *rowptr, const int32_t *col,
                          const double *gK, const double *gM, double *gX);
 
+/* Gradients of a linear solve with respect to its operators (the adjoint
+ * method of Sec. 3.1, Eq. implicit-full, for the linear relation
+ * f(u; K, M) = (alpha M + beta K) u - b of Sec. 5.2; the MCF step of Sec. 7.1
+ * is the case alpha = 1, beta = tau, b = M x). With u solving
+ * (alpha M + beta K) u = b and lambda solving the same (symmetric) system with
+ * the loss gradient dl/du on the right-hand side, dl/dA = -lambda u^T, so on
+ * the CSR pattern:
+ *   gK[t] = -beta * sum_c lambda[i,c] u[j,c]          (slot t = (i, j))
+ *   gM[i] = -alpha * sum_c lambda[i,c] u[i,c]
+ *           + sum_c lambda[i,c] f[i,c]                (only when b = M f, f != NULL)
+ * lambda, u, f: nV x k. */
+int orc_linear_solve_vjp(int32_t nV, const int32_t *rowptr, const int32_t *col, double alpha,
+                         double beta, int32_t k, const double *lambda, const double *u,
+                         const double *f, double *gK, double *gM);
+
 #endif
