@@ -407,6 +407,34 @@ def suite(args, dgo, torch, meshgen):
     out["diff_batch_ico5"] = ent
     del m, Xb, Kb, Mb, gK, gM
 
+    # one differentiable implicit MCF step (Sec. 7.1) on the icosphere L7:
+    # forward (assemble, b = M X, PCG on (M + tau K) u = b, 3 columns) and
+    # backward (adjoint PCG, solve VJP, assembly VJP, M lambda)
+    log(args, "suite: MCF step L7")
+    X, F = meshgen.icosphere(args.level, 1e-3, 0)
+    m = dgo.Mesh(torch.from_numpy(F).to(dev), X.shape[0])
+    W = torch.from_numpy(meshgen.normal(3, X.size).reshape(X.shape)).to(dev, td)
+    Xd = torch.from_numpy(X).to(dev, td)
+    tau, rtol = 1e-3, 1e-10
+    fw, bw = [], []
+    for r in range(reps + 2):
+        Xg = Xd.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u = dgo.mcf_step(m, Xg, tau, rtol=rtol)
+        loss = (u * W).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r >= 2:
+            fw.append((t1 - t0) * 1e3)
+            bw.append((t2 - t1) * 1e3)
+    out["mcf_step_L7"] = {"nV": m.nV, "nF": m.n_elem, "tau": tau, "rtol": rtol, "columns": 3,
+                          "forward_ms": float(np.median(fw)), "backward_ms": float(np.median(bw))}
+    del m, W, Xd, Xg, u, loss
+
     # size sweep past the 256 MB last-level cache: icosphere L8 and L9
     for L in (8, 9):
         log(args, f"suite: icosphere L{L}")

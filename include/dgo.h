@@ -220,6 +220,24 @@ dgo_status dgo_pcg(const dgo_mesh *mesh, dgo_dtype dtype, double alpha, const vo
                    int32_t k, const void *d_b, void *d_u, const dgo_cg_opts *opts,
                    dgo_cg_report *h_rep, dgo_stream stream);
 
+/* Gradients of a linear solve with respect to its operators: the adjoint
+ * method (Sec. 3.1, Eq. implicit-full) applied to the linear relation
+ * (alpha M + beta K) u - b = 0 of the solves of Sec. 5.2 (the implicit MCF
+ * step of Sec. 7.1 is alpha = 1, beta = tau, b = M x). Given the solution u
+ * and the adjoint solution lambda of the same symmetric system with the loss
+ * gradient dl/du on the right-hand side (a second dgo_pcg call), dl/dA =
+ * -lambda u^T restricted to the CSR pattern:
+ *   d_gK[t] = -beta  sum_c lambda[i,c] u[j,c]       for CSR slot t = (i, j)
+ *   d_gM[i] = -alpha sum_c lambda[i,c] u[i,c] + sum_c lambda[i,c] f[i,c]
+ * where the last term (the right-hand side b = M f depends on M) is present
+ * only when d_f is given. d_lambda, d_u, d_f: nV x k; d_gK: nnz; d_gM: nV;
+ * the outputs are overwritten. Sums run over c in ascending order
+ * (deterministic). DGO_ERR_INVALID_ARG for NULL outputs or inputs (other than
+ * d_f), k outside [1, 64] or a bad dtype. */
+dgo_status dgo_linear_solve_vjp(const dgo_mesh *mesh, dgo_dtype dtype, double alpha, double beta,
+                                int32_t k, const void *d_lambda, const void *d_u, const void *d_f,
+                                void *d_gK, void *d_gM, dgo_stream stream);
+
 /* ----------------------------------------------------------------- tracing */
 
 /* Kernel timing for measurement (not part of the method). While enabled,

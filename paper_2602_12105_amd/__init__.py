@@ -19,8 +19,9 @@ import torch
 from ._lib import (DGO_F32, DGO_F64, AssembleOpts, CgOpts, CgReport, DgoError, Sizes, check,
                    lib)
 
-__all__ = ["Mesh", "assemble", "assemble_vjp", "spmv", "pcg", "AssembleFn", "DgoError",
-           "library_path", "build", "trace_enable", "trace_read", "trace_reset"]
+__all__ = ["Mesh", "assemble", "assemble_vjp", "spmv", "pcg", "linear_solve_vjp", "AssembleFn",
+           "LinearSolveFn", "mcf_step", "DgoError", "library_path", "build", "trace_enable",
+           "trace_read", "trace_reset"]
 
 
 def build():
@@ -200,6 +201,53 @@ def pcg(mesh: Mesh, alpha, M, beta, K, b, u0=None, mask=None, g=None, rtol=1e-8,
     report = {"converged_all": bool(rep.converged_all), "iters": list(rep.iters[:k]),
               "relres": list(rep.relres[:k]), "true_relres": list(rep.true_relres[:k])}
     return u, report
+
+
+def linear_solve_vjp(mesh: Mesh, alpha, beta, lam, u, f=None):
+    """Gradients (gK, gM) of a solve (alpha M + beta K) u = b with respect to K
+    and M, given the adjoint solution lam (b = M f when f is given)."""
+    _need(lam, "lam")
+    _need(u, "u", lam.dtype, lam.shape)
+    if f is not None:
+        _need(f, "f", lam.dtype, lam.shape)
+    k = 1 if lam.dim() == 1 else lam.shape[1]
+    gK = torch.empty(mesh.nnz, dtype=lam.dtype, device=lam.device)
+    gM = torch.empty(mesh.nV, dtype=lam.dtype, device=lam.device)
+    check(lib().dgo_linear_solve_vjp(mesh.handle, _dtype_code(lam.dtype), float(alpha),
+                                     float(beta), k, _ptr(lam), _ptr(u), _ptr(f), _ptr(gK),
+                                     _ptr(gM), _stream()), "dgo_linear_solve_vjp")
+    return gK, gM
+
+
+class LinearSolveFn(torch.autograd.Function):
+    """u = (alpha M + beta K)^-1 (M f) by PCG, differentiable in K, M and f by
+    the adjoint method: the backward solves the same (symmetric) system with
+    the incoming gradient, then forms gK, gM on the CSR pattern and gf = M lam."""
+
+    @staticmethod
+    def forward(ctx, K, M, f, mesh, alpha, beta, rtol, max_iter):
+        f = f.contiguous()
+        b = spmv(mesh, 1.0, M, 0.0, K, f)  # b = M f
+        u, _ = pcg(mesh, alpha, M, beta, K, b, rtol=rtol, max_iter=max_iter)
+        ctx.save_for_backward(K, M, f, u)
+        ctx.args = (mesh, alpha, beta, rtol, max_iter)
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        K, M, f, u = ctx.saved_tensors
+        mesh, alpha, beta, rtol, max_iter = ctx.args
+        lam, _ = pcg(mesh, alpha, M, beta, K, gu.contiguous(), rtol=rtol, max_iter=max_iter)
+        gK, gM = linear_solve_vjp(mesh, alpha, beta, lam, u, f)
+        gf = spmv(mesh, 1.0, M, 0.0, K, lam)  # M lam
+        return gK, gM, gf, None, None, None, None, None
+
+
+def mcf_step(mesh: Mesh, X, tau, rtol=1e-10, max_iter=10000):
+    """One implicit mean-curvature-flow step (Sec. 7.1), u = (M + tau K)^-1 M X
+    with K(X), M(X) assembled from X, differentiable in X (triangle meshes)."""
+    K, M = AssembleFn.apply(X, mesh)
+    return LinearSolveFn.apply(K, M, X, mesh, 1.0, tau, rtol, max_iter)
 
 
 class AssembleFn(torch.autograd.Function):

@@ -85,6 +85,7 @@ SIGNATURES = {
     "dgo_spmv": (C.c_int, [P, C.c_int, i32, f64, P, f64, P, i32, P, P, P]),
     "dgo_pcg": (C.c_int, [P, C.c_int, f64, P, f64, P, P, P, i32, P, P, C.POINTER(CgOpts),
                           C.POINTER(CgReport), P]),
+    "dgo_linear_solve_vjp": (C.c_int, [P, C.c_int, f64, f64, i32, P, P, P, P, P, P]),
     "dgo_trace_enable": (C.c_int, [i32, C.c_char_p]),
     "dgo_trace_read": (C.c_int, [C.POINTER(TraceEntry), i32, C.POINTER(i32)]),
     "dgo_trace_reset": (None, []),

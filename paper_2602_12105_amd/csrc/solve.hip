@@ -84,6 +84,36 @@ k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     }
 }
 
+// Gradients of a linear solve with respect to K and M (see
+// dgo_linear_solve_vjp): one thread per row, sums over the columns c in
+// ascending order.
+template <typename R>
+__global__ void k_solve_vjp(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                            int32_t nV, R alpha, R beta, int k, const R *__restrict__ lam,
+                            const R *__restrict__ u, const R *__restrict__ f,
+                            R *__restrict__ gK, R *__restrict__ gM) {
+    const int64_t i = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (i >= nV) return;
+    const R *li = lam + i * k;
+    for (int32_t t = rowptr[i]; t < rowptr[i + 1]; ++t) {
+        const R *uj = u + (int64_t)col[t] * k;
+        R s = 0;
+        for (int c = 0; c < k; ++c) s += li[c] * uj[c];
+        gK[t] = -beta * s;
+    }
+    const R *ui = u + i * k;
+    R m = 0;
+    for (int c = 0; c < k; ++c) m += li[c] * ui[c];
+    R g = -alpha * m;
+    if (f) {
+        const R *fi = f + i * k;
+        R q = 0;
+        for (int c = 0; c < k; ++c) q += li[c] * fi[c];
+        g += q;
+    }
+    gM[i] = g;
+}
+
 // ------------------------------------------------------------------- PCG
 
 // q = A_II p (q_B = 0), from M and K (A x0 at the start of a solve). With
@@ -796,4 +826,30 @@ extern "C" dgo_status dgo_pcg(const dgo_mesh *m, dgo_dtype dtype, double alpha, 
                                h_rep, s);
     return run_pcg<float>(m, alpha, (const float *)d_Mdiag, beta, (const float *)d_Kvals, d_mask,
                           (const float *)d_g, k, (const float *)d_b, (float *)d_u, o, h_rep, s);
+}
+
+extern "C" dgo_status dgo_linear_solve_vjp(const dgo_mesh *m, dgo_dtype dtype, double alpha,
+                                           double beta, int32_t k, const void *d_lambda,
+                                           const void *d_u, const void *d_f, void *d_gK,
+                                           void *d_gM, dgo_stream stream) {
+    clear_error();
+    if (!m || !d_lambda || !d_u || !d_gK || !d_gM)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_linear_solve_vjp: NULL argument");
+    if (k < 1 || k > kMaxK) return fail(DGO_ERR_INVALID_ARG, "dgo_linear_solve_vjp: k must be in [1, 64]");
+    if (dtype != DGO_F32 && dtype != DGO_F64)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_linear_solve_vjp: bad dtype");
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == DGO_F64)
+        DGO_LAUNCH("solve_vjp", s,
+                   k_solve_vjp<double><<<grid_for(m->nV, T), T, 0, s>>>(
+                       m->rowptr, m->col, m->nV, alpha, beta, k, (const double *)d_lambda,
+                       (const double *)d_u, (const double *)d_f, (double *)d_gK, (double *)d_gM));
+    else
+        DGO_LAUNCH("solve_vjp", s,
+                   k_solve_vjp<float><<<grid_for(m->nV, T), T, 0, s>>>(
+                       m->rowptr, m->col, m->nV, (float)alpha, (float)beta, k,
+                       (const float *)d_lambda, (const float *)d_u, (const float *)d_f,
+                       (float *)d_gK, (float *)d_gM));
+    DGO_HIP(hipGetLastError());
+    return DGO_OK;
 }

@@ -50,6 +50,10 @@ def test_rejects_bad_arguments_without_device(dgo):
     assert dgo.dgo_spmv(None, 1, 1, 1.0, None, 1.0, None, 1, None, None, None) == 1
     assert dgo.dgo_pcg(None, 1, 1.0, None, 1.0, None, None, None, 1, None, None, None, None,
                        None) == 1
+    assert dgo.dgo_linear_solve_vjp(None, 1, 1.0, 1.0, 1, None, None, None, None, None,
+                                    None) == 1
+    assert b"NULL" in dgo.dgo_last_error()
+    assert dgo.dgo_assemble_vjp(None, 1, 1, None, None, None, None, None) == 1
     dgo.dgo_mesh_destroy(None)
 
 

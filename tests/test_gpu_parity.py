@@ -346,6 +346,48 @@ def test_vjp_row_block_and_long_rows(shape):
         assert np.abs(gX - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("dtype,with_f", [("f64", True), ("f64", False), ("f32", True)])
+def test_linear_solve_vjp_parity(dtype, with_f):
+    print(f"[solve-vjp] ico5 {dtype} f={with_f}", flush=True)
+    X, F = meshgen.icosphere(5, 1e-2, 9)
+    m = dgo.Mesh(torch.from_numpy(F).to(DEV), X.shape[0])
+    td = torch.float64 if dtype == "f64" else torch.float32
+    k = 3
+    lam = torch.from_numpy(meshgen.normal(21, m.nV * k).reshape(-1, k)).to(DEV, td)
+    u = torch.from_numpy(meshgen.normal(22, m.nV * k).reshape(-1, k)).to(DEV, td)
+    f = torch.from_numpy(meshgen.normal(23, m.nV * k).reshape(-1, k)).to(DEV, td)
+    gK, gM = dgo.linear_solve_vjp(m, 1.0, 1e-2, lam, u, f if with_f else None)
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    L, U, Fh = (t.double().cpu().numpy() for t in (lam, u, f))
+    rK, rM = oracle.linear_solve_vjp(rp, col, 1.0, 1e-2, L, U, Fh if with_f else None)
+    # error scale: the sums of |terms| (beta |lam_i| . |u_j| per slot)
+    rows = np.repeat(np.arange(m.nV), np.diff(rp))
+    sK = 1e-2 * np.sum(np.abs(L[rows]) * np.abs(U[col]), 1)
+    sM = np.sum(np.abs(L) * np.abs(U), 1) + (np.sum(np.abs(L) * np.abs(Fh), 1) if with_f else 0)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert np.all(np.abs(gK.double().cpu().numpy() - rK) <= tol * sK)
+    assert np.all(np.abs(gM.double().cpu().numpy() - rM) <= tol * sM)
+
+
+def test_mcf_step_gradient_matches_oracle():
+    """Autograd through AssembleFn and LinearSolveFn (forward PCG, adjoint PCG,
+    solve VJP, assembly VJP) against the oracle's adjoint gradient of one
+    implicit MCF step."""
+    print("[mcf-step] ico4 f64", flush=True)
+    X, F = meshgen.icosphere(4, 1e-2, 10)
+    tau = 1e-2
+    W = meshgen.normal(24, X.size).reshape(X.shape)
+    m = dgo.Mesh(torch.from_numpy(F).to(DEV), X.shape[0])
+    Xd = torch.from_numpy(X).to(DEV).requires_grad_(True)
+    u = dgo.mcf_step(m, Xd, tau, rtol=1e-13, max_iter=5000)
+    loss = (u * torch.from_numpy(W).to(DEV)).sum()
+    loss.backward()
+    lo, go = oracle.mcf_step_grad(X, F, tau, W)
+    assert abs(loss.item() - lo) <= 1e-10 * abs(lo)
+    g = Xd.grad.cpu().numpy()
+    assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
+
+
 def test_autograd_loss_gradient_cfg5():
     """loss = u^T K(x) u + total area through AssembleFn matches the oracle gradient."""
     print("[autograd] batch of icosphere L5", flush=True)
