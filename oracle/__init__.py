@@ -55,6 +55,9 @@ def lib():
             "orc_loss_cstep_tri": [i32, i64, P, P, P, i32, i32, f64, P],
             "orc_assemble_vjp_tri": [i32, i64, P, P, P, P, P, P, P],
             "orc_linear_solve_vjp": [i32, P, P, f64, f64, i32, P, P, P, P, P],
+            "orc_assemble_intrinsic": [i32, i64, P, P, P, P, P, P],
+            "orc_face_gradient": [i32, i64, P, P, i32, P, P],
+            "orc_face_divergence": [i32, i64, P, P, i32, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -252,3 +255,39 @@ def mcf_step_grad(X, F, tau, W, rtol=1e-14, max_iter=20000):
     gK, gM = linear_solve_vjp(rp, col, 1.0, tau, lam, u, X)
     gX = assemble_vjp_tri(X, F, rp, col, gK, gM) + M[:, None] * lam
     return float(np.sum(_f64(W) * u)), gX
+
+
+def assemble_intrinsic(F, nV, lengths, rowptr=None, col=None):
+    """(Kvals, Mdiag) from edge lengths indexed like EV."""
+    F = _i32(F)
+    if rowptr is None:
+        EV, _, _ = edges(nV, F)
+        rowptr, col = csr(nV, EV)
+    rowptr, col = _i32(rowptr), _i32(col)
+    K = np.empty(int(rowptr[-1]))
+    M = np.empty(nV)
+    _check(lib().orc_assemble_intrinsic(nV, F.shape[0], _p(F), _p(_f64(lengths)), _p(rowptr),
+                                        _p(col), _p(K), _p(M)), "assemble_intrinsic")
+    return K, M
+
+
+def face_gradient(X, F, u):
+    """(G u) per face: nF x k x 3 for u of shape (nV,) or (nV, k)."""
+    X, F = _f64(X), _i32(F)
+    u = _f64(u).reshape(X.shape[0], -1)
+    k = u.shape[1]
+    g = np.empty((F.shape[0], k, 3))
+    _check(lib().orc_face_gradient(X.shape[0], F.shape[0], _p(F), _p(X), k, _p(u), _p(g)),
+           "face_gradient")
+    return g
+
+
+def face_divergence(X, F, y):
+    """(D y) per vertex: nV x k for y of shape (nF, k, 3)."""
+    X, F = _f64(X), _i32(F)
+    y = _f64(y).reshape(F.shape[0], -1, 3)
+    k = y.shape[1]
+    d = np.empty((X.shape[0], k))
+    _check(lib().orc_face_divergence(X.shape[0], F.shape[0], _p(F), _p(X), k, _p(y), _p(d)),
+           "face_divergence")
+    return d

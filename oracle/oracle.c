@@ -689,3 +689,121 @@ int orc_linear_solve_vjp(int32_t nV, const int32_t *rowptr, const int32_t *col, 
     }
     return ORC_OK;
 }
+
+/* Area from three edge lengths: Heron's formula in Kahan's stable form
+ * (sorted a >= b >= c, "Miscalculating Area and Angles of a Needle-like
+ * Triangle"). */
+static double heron_area(double a, double b, double c) {
+    double t;
+    if (a < b) { t = a; a = b; b = t; }
+    if (a < c) { t = a; a = c; c = t; }
+    if (b < c) { t = b; b = c; c = t; }
+    double q = (a + (b + c)) * (c - (a - b)) * (c + (a - b)) * (a + (b - c));
+    return q > 0.0 ? 0.25 * sqrt(q) : 0.0;
+}
+
+int orc_assemble_intrinsic(int32_t nV, int64_t nF, const int32_t *F, const double *lengths,
+                           const int32_t *rowptr, const int32_t *col, double *Kvals,
+                           double *Mdiag) {
+    int st = orc_validate(2, nV, nF, F);
+    if (st) return st;
+    if (!lengths || !rowptr || !col || !Kvals || !Mdiag) return ORC_ERR_INVALID_ARG;
+    int64_t cap = nF * 3;
+    int32_t *EV = (int32_t *)malloc(sizeof(int32_t) * 2 * (cap ? cap : 1));
+    int32_t *ee = (int32_t *)malloc(sizeof(int32_t) * (cap ? cap : 1));
+    int8_t *es = (int8_t *)malloc(cap ? cap : 1);
+    double *w = (double *)malloc(sizeof(double) * (cap ? cap : 1));
+    if (!EV || !ee || !es || !w) { free(EV); free(ee); free(es); free(w); return ORC_ERR_NOMEM; }
+    int64_t nE = 0;
+    st = orc_edges(2, nV, nF, F, EV, &nE, ee, es);
+    if (st == ORC_OK) {
+        for (int64_t e = 0; e < nE; ++e) w[e] = 0.0;
+        for (int32_t i = 0; i < nV; ++i) Mdiag[i] = 0.0;
+        for (int64_t t = 0; t < nF && st == ORC_OK; ++t) {
+            double l[3];
+            for (int j = 0; j < 3; ++j) l[j] = lengths[ee[3 * t + j]];
+            double A = heron_area(l[0], l[1], l[2]);
+            if (A == 0.0) { st = ORC_ERR_DEGENERATE; break; }
+            for (int j = 0; j < 3; ++j) {
+                double lj1 = l[(j + 1) % 3], lj2 = l[(j + 2) % 3];
+                double cot = (lj1 * lj1 + lj2 * lj2 - l[j] * l[j]) / (4.0 * A);
+                w[ee[3 * t + j]] += 0.5 * cot;
+            }
+            for (int j = 0; j < 3; ++j) Mdiag[F[3 * t + j]] += A / 3.0;
+        }
+        if (st == ORC_OK) {
+            int64_t nnz = rowptr[nV];
+            for (int64_t t = 0; t < nnz; ++t) Kvals[t] = 0.0;
+            for (int64_t e = 0; e < nE; ++e) {
+                int32_t a = EV[2 * e], b = EV[2 * e + 1];
+                int64_t sab = find_slot(rowptr, col, a, b), sba = find_slot(rowptr, col, b, a);
+                int64_t saa = find_slot(rowptr, col, a, a), sbb = find_slot(rowptr, col, b, b);
+                if (sab < 0 || sba < 0 || saa < 0 || sbb < 0) { st = ORC_ERR_INVALID_ARG; break; }
+                Kvals[sab] = -w[e];
+                Kvals[sba] = -w[e];
+                Kvals[saa] += w[e];
+                Kvals[sbb] += w[e];
+            }
+        }
+    }
+    free(EV); free(ee); free(es); free(w);
+    return st;
+}
+
+/* grad phi_j of the face's three vertices and its area */
+static void face_grads(const double *x0, const double *x1, const double *x2, double g[3][3],
+                       double *area) {
+    const double *x[3] = {x0, x1, x2};
+    double e1[3], e2[3], n[3];
+    for (int c = 0; c < 3; ++c) { e1[c] = x1[c] - x0[c]; e2[c] = x2[c] - x0[c]; }
+    n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    *area = 0.5 * sqrt(nn);
+    for (int j = 0; j < 3; ++j) {
+        const double *p = x[(j + 1) % 3], *q = x[(j + 2) % 3];
+        double e[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+        g[j][0] = (n[1] * e[2] - n[2] * e[1]) / nn;
+        g[j][1] = (n[2] * e[0] - n[0] * e[2]) / nn;
+        g[j][2] = (n[0] * e[1] - n[1] * e[0]) / nn;
+    }
+}
+
+int orc_face_gradient(int32_t nV, int64_t nF, const int32_t *F, const double *X, int32_t k,
+                      const double *u, double *g) {
+    int st = orc_validate(2, nV, nF, F);
+    if (st) return st;
+    if (k < 1 || !X || !u || !g) return ORC_ERR_INVALID_ARG;
+    for (int64_t t = 0; t < nF; ++t) {
+        const int32_t *v = F + 3 * t;
+        double gr[3][3], A;
+        face_grads(X + 3 * v[0], X + 3 * v[1], X + 3 * v[2], gr, &A);
+        for (int32_t c = 0; c < k; ++c)
+            for (int d = 0; d < 3; ++d) {
+                double s = 0.0;
+                for (int j = 0; j < 3; ++j) s += u[(int64_t)v[j] * k + c] * gr[j][d];
+                g[(t * k + c) * 3 + d] = s;
+            }
+    }
+    return ORC_OK;
+}
+
+int orc_face_divergence(int32_t nV, int64_t nF, const int32_t *F, const double *X, int32_t k,
+                        const double *y, double *div) {
+    int st = orc_validate(2, nV, nF, F);
+    if (st) return st;
+    if (k < 1 || !X || !y || !div) return ORC_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < (int64_t)nV * k; ++i) div[i] = 0.0;
+    for (int64_t t = 0; t < nF; ++t) {
+        const int32_t *v = F + 3 * t;
+        double gr[3][3], A;
+        face_grads(X + 3 * v[0], X + 3 * v[1], X + 3 * v[2], gr, &A);
+        for (int j = 0; j < 3; ++j)
+            for (int32_t c = 0; c < k; ++c) {
+                const double *yf = y + (t * k + c) * 3;
+                div[(int64_t)v[j] * k + c] -= A * (gr[j][0] * yf[0] + gr[j][1] * yf[1] + gr[j][2] * yf[2]);
+            }
+    }
+    return ORC_OK;
+}

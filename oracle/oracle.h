@@ -112,4 +112,29 @@ int orc_linear_solve_vjp(int32_t nV, const int32_t *rowptr, const int32_t *col, 
                          double beta, int32_t k, const double *lambda, const double *u,
                          const double *f, double *gK, double *gM);
 
+/* Intrinsic assembly (Sec. 7.3, the intrinsic cotangent weights of the SCP
+ * example): K and M of a triangle mesh from its edge lengths alone. lengths
+ * is indexed like EV (the sorted (min, max) edges of orc_edges). For a
+ * triangle with edge lengths l_j (edge opposite local vertex j) and area A
+ * (Heron's formula in Kahan's stable form), the angle at vertex j has
+ * cot = (l_{j+1}^2 + l_{j+2}^2 - l_j^2) / (4 A); K and M then follow as in
+ * orc_assemble (w_ij = sum of 1/2 cot over the triangles on edge ij,
+ * M_ii = sum of A / 3). */
+int orc_assemble_intrinsic(int32_t nV, int64_t nF, const int32_t *F, const double *lengths,
+                           const int32_t *rowptr, const int32_t *col, double *Kvals,
+                           double *Mdiag);
+
+/* Per-face gradient G (Sec. 7.4: the gradient operator of the geodesic
+ * example) of k vertex fields u (nV x k): (G u)_f = sum_j u[v_j] grad phi_j,
+ * grad phi_j = (n x e_j) / |n|^2 with n = (x1 - x0) x (x2 - x0) and e_j =
+ * x_{j+2} - x_{j+1} the edge opposite local vertex j. g: nF x k x 3. */
+int orc_face_gradient(int32_t nV, int64_t nF, const int32_t *F, const double *X, int32_t k,
+                      const double *u, double *g);
+
+/* Divergence D = -G^T diag(A_f): (D y)_i = -sum over faces f of i of
+ * A_f grad phi_i . y_f, for k face vector fields y (nF x k x 3); div: nV x k.
+ * With these definitions D G = -K (K the cotangent stiffness). */
+int orc_face_divergence(int32_t nV, int64_t nF, const int32_t *F, const double *X, int32_t k,
+                        const double *y, double *div);
+
 #endif
