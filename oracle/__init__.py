@@ -272,21 +272,21 @@ def assemble_intrinsic(F, nV, lengths, rowptr=None, col=None):
 
 
 def face_gradient(X, F, u):
-    """(G u) per face: nF x k x 3 for u of shape (nV,) or (nV, k)."""
+    """(G u) per face, component-major: (k, 3, nF) for u of shape (nV,) or (nV, k)."""
     X, F = _f64(X), _i32(F)
     u = _f64(u).reshape(X.shape[0], -1)
     k = u.shape[1]
-    g = np.empty((F.shape[0], k, 3))
+    g = np.empty((k, 3, F.shape[0]))
     _check(lib().orc_face_gradient(X.shape[0], F.shape[0], _p(F), _p(X), k, _p(u), _p(g)),
            "face_gradient")
     return g
 
 
 def face_divergence(X, F, y):
-    """(D y) per vertex: nV x k for y of shape (nF, k, 3)."""
+    """(D y) per vertex: (nV, k) for y of shape (k, 3, nF) or (3, nF)."""
     X, F = _f64(X), _i32(F)
-    y = _f64(y).reshape(F.shape[0], -1, 3)
-    k = y.shape[1]
+    y = _f64(y).reshape(-1, 3, F.shape[0])
+    k = y.shape[0]
     d = np.empty((X.shape[0], k))
     _check(lib().orc_face_divergence(X.shape[0], F.shape[0], _p(F), _p(X), k, _p(y), _p(d)),
            "face_divergence")

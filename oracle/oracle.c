@@ -783,7 +783,7 @@ int orc_face_gradient(int32_t nV, int64_t nF, const int32_t *F, const double *X,
             for (int d = 0; d < 3; ++d) {
                 double s = 0.0;
                 for (int j = 0; j < 3; ++j) s += u[(int64_t)v[j] * k + c] * gr[j][d];
-                g[(t * k + c) * 3 + d] = s;
+                g[((int64_t)c * 3 + d) * nF + t] = s;
             }
     }
     return ORC_OK;
@@ -801,8 +801,9 @@ int orc_face_divergence(int32_t nV, int64_t nF, const int32_t *F, const double *
         face_grads(X + 3 * v[0], X + 3 * v[1], X + 3 * v[2], gr, &A);
         for (int j = 0; j < 3; ++j)
             for (int32_t c = 0; c < k; ++c) {
-                const double *yf = y + (t * k + c) * 3;
-                div[(int64_t)v[j] * k + c] -= A * (gr[j][0] * yf[0] + gr[j][1] * yf[1] + gr[j][2] * yf[2]);
+                const double *yc = y + (int64_t)c * 3 * nF + t;
+                div[(int64_t)v[j] * k + c] +=
+                    A * (gr[j][0] * yc[0] + gr[j][1] * yc[nF] + gr[j][2] * yc[2 * nF]);
             }
     }
     return ORC_OK;

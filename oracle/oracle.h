@@ -125,15 +125,18 @@ int orc_assemble_intrinsic(int32_t nV, int64_t nF, const int32_t *F, const doubl
                            double *Mdiag);
 
 /* Per-face gradient G (Sec. 7.4: the gradient operator of the geodesic
- * example) of k vertex fields u (nV x k): (G u)_f = sum_j u[v_j] grad phi_j,
- * grad phi_j = (n x e_j) / |n|^2 with n = (x1 - x0) x (x2 - x0) and e_j =
- * x_{j+2} - x_{j+1} the edge opposite local vertex j. g: nF x k x 3. */
+ * example) of k vertex fields u (nV x k, row-major): (G u)_f = sum_j u[v_j]
+ * grad phi_j, grad phi_j = (n x e_j) / |n|^2 with n = (x1 - x0) x (x2 - x0)
+ * and e_j = x_{j+2} - x_{j+1} the edge opposite local vertex j. g is
+ * component-major like the (3, nF) face fields of that example: component d
+ * of field c on face f at g[(c * 3 + d) * nF + f]. */
 int orc_face_gradient(int32_t nV, int64_t nF, const int32_t *F, const double *X, int32_t k,
                       const double *u, double *g);
 
-/* Divergence D = -G^T diag(A_f): (D y)_i = -sum over faces f of i of
- * A_f grad phi_i . y_f, for k face vector fields y (nF x k x 3); div: nV x k.
- * With these definitions D G = -K (K the cotangent stiffness). */
+/* Divergence D = G^T diag(A_f): (D y)_i = sum over the faces f of i of
+ * A_f grad phi_i . y_f, for k face vector fields y in the layout of g above;
+ * div: nV x k. The sign is the one the u-update of the geodesic ADMM loop
+ * (Sec. 7.4) needs with an SPD Laplacian: D G = K, the cotangent stiffness. */
 int orc_face_divergence(int32_t nV, int64_t nF, const int32_t *F, const double *X, int32_t k,
                         const double *y, double *div);
 

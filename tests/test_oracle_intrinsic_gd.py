@@ -3,9 +3,10 @@ per-face gradient G and divergence D: closed forms of single triangles, the
 extrinsic assembly (a different formula: cross and dot products of positions)
 fed with lengths measured from the same positions, scale invariance of the
 cotangent weights, exactness of G on linear fields (the tangential projection
-of the field's gradient), D G = -K against the pinned cotangent stiffness,
-adjointness of D and G under the area-weighted face inner product, and the
-zero vertex sum of D on a closed surface."""
+of the field's gradient), D G = K against the pinned cotangent stiffness (the
+sign the u-update of the geodesic ADMM loop of Sec. 7.4 needs with an SPD
+Laplacian), adjointness of D and G under the area-weighted face inner product,
+and the zero vertex sum of D on a closed surface."""
 import json
 import os
 
@@ -90,7 +91,7 @@ def test_gradient_of_hat_functions_closed_form(orc):
     F = np.array([[0, 1, 2]], np.int32)
     g = orc.face_gradient(X, F, np.eye(3))  # hat function j as field j
     want = np.array([[-0.5, -1, 0], [0.5, 0, 0], [0, 1, 0]])
-    np.testing.assert_allclose(g[0], want, atol=1e-15)
+    np.testing.assert_allclose(g[:, :, 0], want, atol=1e-15)
 
 
 @pytest.mark.parametrize("name", sorted(MESHES))
@@ -103,21 +104,21 @@ def test_gradient_exact_on_linear_fields(orc, name):
     _, N = areas_normals(X, F)
     for c in range(4):
         proj = a[:, c] - (N @ a[:, c])[:, None] * N
-        np.testing.assert_allclose(g[:, c], proj, atol=1e-11)
+        np.testing.assert_allclose(g[c].T, proj, atol=1e-11)
     # coordinate functions: sum_j x_j (x) grad phi_j = I - N N^T
-    G = orc.face_gradient(X, F, X)
-    P = np.eye(3)[None] - N[:, :, None] * N[:, None, :]
+    G = orc.face_gradient(X, F, X)  # (coordinate, component, face)
+    P = np.eye(3)[:, :, None] - N.T[:, None, :] * N.T[None, :, :]
     np.testing.assert_allclose(G, P, atol=1e-11)
 
 
 @pytest.mark.parametrize("name", sorted(MESHES))
-def test_div_grad_is_minus_cotangent_stiffness(orc, name):
+def test_div_grad_is_cotangent_stiffness(orc, name):
     X, F = MESHES[name]()
     K, M, rp, col = orc.assemble(X, F)
     u = meshgen.normal(11, X.shape[0] * 3).reshape(-1, 3)
     d = orc.face_divergence(X, F, orc.face_gradient(X, F, u))
     Ku = dense(K, rp, col) @ u
-    np.testing.assert_allclose(d, -Ku, rtol=0, atol=1e-11 * np.abs(Ku).max())
+    np.testing.assert_allclose(d, Ku, rtol=0, atol=1e-11 * np.abs(Ku).max())
 
 
 @pytest.mark.parametrize("name", sorted(MESHES))
@@ -125,15 +126,15 @@ def test_divergence_adjoint_of_gradient(orc, name):
     X, F = MESHES[name]()
     A, _ = areas_normals(X, F)
     rng = np.random.default_rng(5)
-    y = rng.standard_normal((F.shape[0], 2, 3))
+    y = rng.standard_normal((2, 3, F.shape[0]))
     u = rng.standard_normal((X.shape[0], 2))
     lhs = np.sum(orc.face_divergence(X, F, y) * u)
-    rhs = -np.sum(A[:, None, None] * y * orc.face_gradient(X, F, u))
+    rhs = np.sum(A[None, None, :] * y * orc.face_gradient(X, F, u))
     assert abs(lhs - rhs) <= 1e-11 * max(1.0, abs(rhs))
 
 
 def test_divergence_sums_to_zero_on_closed_surface(orc):
     X, F = MESHES["ico"]()
-    y = np.random.default_rng(9).standard_normal((F.shape[0], 3, 3))
+    y = np.random.default_rng(9).standard_normal((3, 3, F.shape[0]))
     d = orc.face_divergence(X, F, y)
     assert np.abs(d.sum(axis=0)).max() <= 1e-12 * np.abs(d).sum()
