@@ -86,6 +86,15 @@ def alg_bytes(kind, s, nV, nF, nnz, k):
     if kind == "cg_vupdate":
         # read r w p s x, write p s x r, read D^-1
         return 9 * k * s * nV + s * nV
+    if kind == "assemble_intrinsic":
+        # edge lengths and the face -> edge map read, K and M written
+        return s * (nnz - nV) // 2 + 12 * nF + s * nnz + s * nV
+    if kind == "face_gradient":
+        # positions, triangles and k vertex fields read, k face vectors written
+        return 3 * s * nV + 12 * nF + k * s * nV + 3 * k * s * nF
+    if kind == "face_divergence":
+        # positions, triangles and k face vectors read, k vertex fields written
+        return 3 * s * nV + 12 * nF + 3 * k * s * nF + k * s * nV
     if kind == "cg_values":
         # K, columns, row pointers, M, D^-1 read; scaled values written
         return nnz * (2 * s + 4) + 4 * (nV + 1) + 2 * s * nV
@@ -456,8 +465,32 @@ def suite(args, dgo, torch, meshgen):
                              reps, flush if cold else None)
             ent["spmv_k8_" + tag] = roof(abs_, us)
         ent["triangles_per_s_cold"] = m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
+        # intrinsic assembly from edge lengths, per-face gradient and divergence
+        EVd = m.edges()[0].long()
+        Ld = (Xd[EVd[:, 0]] - Xd[EVd[:, 1]]).norm(dim=1).contiguous()
+        Ki, Mi = dgo.assemble_intrinsic(m, Ld)
+        ab = alg_bytes("assemble_intrinsic", s, m.nV, m.n_elem, m.nnz, 1)
+        for cold in (False, True):
+            us = kernel_time(dgo, torch, lambda: dgo.assemble_intrinsic(m, Ld, out=(Ki, Mi)),
+                             "assemble_intrinsic", reps, flush if cold else None)
+            ent["assemble_intrinsic_" + ("cold" if cold else "warm")] = roof(ab, us)
+        for k in (1, 3):
+            u = torch.randn(m.nV, k, dtype=td, device=dev)
+            g = dgo.face_gradient(m, Xd, u)
+            y = torch.randn(k, 3, m.n_elem, dtype=td, device=dev)
+            d = dgo.face_divergence(m, Xd, y)
+            abg = alg_bytes("face_gradient", s, m.nV, m.n_elem, m.nnz, k)
+            abd = alg_bytes("face_divergence", s, m.nV, m.n_elem, m.nnz, k)
+            for cold in (False, True):
+                tag = f"k{k}_" + ("cold" if cold else "warm")
+                us = kernel_time(dgo, torch, lambda: dgo.face_gradient(m, Xd, u, out=g),
+                                 "face_gradient", reps, flush if cold else None)
+                ent["face_gradient_" + tag] = roof(abg, us)
+                us = kernel_time(dgo, torch, lambda: dgo.face_divergence(m, Xd, y, out=d),
+                                 "face_divergence", reps, flush if cold else None)
+                ent["face_divergence_" + tag] = roof(abd, us)
         out[f"icosphere_L{L}"] = ent
-        del m, K, M, Xd, xk, yk
+        del m, K, M, Xd, xk, yk, Ki, Mi, Ld, u, g, y, d
     del flush
     torch.cuda.empty_cache()
     return out

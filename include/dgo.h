@@ -172,6 +172,50 @@ dgo_status dgo_assemble_vjp(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch
                             const void *d_X, const void *d_gK, const void *d_gM, void *d_gX,
                             dgo_stream stream);
 
+/* Intrinsic assembly (the intrinsic cotangent weights of the SCP example,
+ * Sec. 7.3): K and M of a triangle mesh from its edge lengths alone. For a
+ * triangle with edge lengths l_j (edge opposite local vertex j) and area A
+ * (Heron's formula in Kahan's stable form), the weight of the angle at vertex
+ * j is 1/2 cot = (l_{j+1}^2 + l_{j+2}^2 - l_j^2) / (8 A); K and M then follow
+ * as in dgo_assemble (w_ij summed over the triangles on edge ij, M_ii = sum of
+ * A / 3). d_lengths (batch x nE) is indexed like the mesh's edges
+ * (dgo_mesh_edges order); d_Kvals (batch x nnz), d_Mdiag (batch x nV). opts
+ * and h_n_degenerate as in dgo_assemble (lengths that violate the triangle
+ * inequality count as zero-area triangles). Bitwise deterministic and
+ * symmetric. The first call on a mesh allocates its per-incidence face list
+ * (4 bytes per vertex-face incidence). dim 3 meshes return
+ * DGO_ERR_UNSUPPORTED. */
+dgo_status dgo_assemble_intrinsic(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch,
+                                  const void *d_lengths, const dgo_assemble_opts *opts,
+                                  void *d_Kvals, void *d_Mdiag, int64_t *h_n_degenerate,
+                                  dgo_stream stream);
+
+/* ------------------------------------------------ face gradient, divergence */
+
+/* Per-face gradient G (the gradient operator of the geodesic example,
+ * Sec. 7.4) of k vertex fields: (G u)_f = sum_j u[v_j] grad phi_j with
+ * grad phi_j = (n x e_j) / |n|^2, n = (x1 - x0) x (x2 - x0), e_j = x_{j+2} -
+ * x_{j+1} the edge opposite local vertex j. d_X (nV x 3), d_u (nV x k,
+ * row-major), 1 <= k <= 64; d_g (k x 3 x nF, component-major: component d of
+ * field c on face f at [(c * 3 + d) * nF + f], the (3, nF) face-field layout
+ * of that example) is overwritten. Triangle meshes only (else
+ * DGO_ERR_UNSUPPORTED). Zero-area faces give non-finite values. */
+dgo_status dgo_face_gradient(const dgo_mesh *mesh, dgo_dtype dtype, const void *d_X, int32_t k,
+                             const void *d_u, void *d_g, dgo_stream stream);
+
+/* Divergence D = G^T diag(A_f) (the divergence operator of Sec. 7.4, with the
+ * sign its u-update needs when the Laplacian is the SPD stiffness: D G = K):
+ * (D y)_i = sum over the faces f of vertex i of A_f grad phi_i . y_f. d_y
+ * (k x 3 x nF, the layout of dgo_face_gradient's output), d_div (nV x k) is
+ * overwritten. Each sum runs over the vertex's faces in ascending face order:
+ * deterministic. The per-face corner terms are staged in the mesh's
+ * workspace (3 k nF values, grown on demand and shared with the mesh's other
+ * calls, so calls on one mesh must not overlap); the first call on a mesh
+ * also allocates its per-incidence face lists (8 bytes per vertex-face
+ * incidence). Triangle meshes with fewer than 2^31 / 3 faces only. */
+dgo_status dgo_face_divergence(const dgo_mesh *mesh, dgo_dtype dtype, const void *d_X, int32_t k,
+                               const void *d_y, void *d_div, dgo_stream stream);
+
 /* --------------------------------------------------------- operator apply */
 
 /* y = (alpha M + beta K) x for `batch` operator instances and k columns:

@@ -21,7 +21,7 @@ from ._lib import (DGO_F32, DGO_F64, AssembleOpts, CgOpts, CgReport, DgoError, S
 
 __all__ = ["Mesh", "assemble", "assemble_vjp", "spmv", "pcg", "linear_solve_vjp", "AssembleFn",
            "LinearSolveFn", "mcf_step", "DgoError", "library_path", "build", "trace_enable",
-           "trace_read", "trace_reset"]
+           "trace_read", "trace_reset", "assemble_intrinsic", "face_gradient", "face_divergence"]
 
 
 def build():
@@ -148,6 +148,64 @@ def assemble(mesh: Mesh, X: torch.Tensor, clamp_min=None, check_degenerate=False
     check(lib().dgo_assemble(mesh.handle, dt, b, _ptr(X), opts, _ptr(K), _ptr(M),
                              C.byref(nd) if check_degenerate else None, _stream()), "dgo_assemble")
     return K, M
+
+
+def assemble_intrinsic(mesh: Mesh, lengths: torch.Tensor, clamp_min=None,
+                       check_degenerate=False, out=None):
+    """K (CSR values) and lumped M of a triangle mesh from its edge lengths,
+    (nE,) or (batch, nE) in the mesh's edge order."""
+    _need(lengths, "lengths")
+    if lengths.dim() == 1:
+        b, batched = 1, False
+        _need(lengths, "lengths", shape=(mesh.nE,))
+    else:
+        b, batched = lengths.shape[0], True
+        _need(lengths, "lengths", shape=(b, mesh.nE))
+    dt = _dtype_code(lengths.dtype)
+    if out is None:
+        dev, ty = lengths.device, lengths.dtype
+        K = torch.empty((b, mesh.nnz) if batched else (mesh.nnz,), dtype=ty, device=dev)
+        M = torch.empty((b, mesh.nV) if batched else (mesh.nV,), dtype=ty, device=dev)
+    else:
+        K, M = out
+    opts = None
+    if clamp_min is not None:
+        opts = C.byref(AssembleOpts(1, float(clamp_min)))
+    nd = C.c_int64(0)
+    check(lib().dgo_assemble_intrinsic(mesh.handle, dt, b, _ptr(lengths), opts, _ptr(K), _ptr(M),
+                                       C.byref(nd) if check_degenerate else None, _stream()),
+          "dgo_assemble_intrinsic")
+    return K, M
+
+
+def face_gradient(mesh: Mesh, X: torch.Tensor, u: torch.Tensor, out=None):
+    """Per-face gradients of vertex fields u ((nV,) or (nV, k)): a (k, 3, nF)
+    tensor (component-major face fields)."""
+    _need(X, "X", shape=(mesh.nV, 3))
+    _need(u, "u", X.dtype)
+    k = 1 if u.dim() == 1 else u.shape[1]
+    if u.shape[0] != mesh.nV:
+        raise ValueError("u must have nV rows")
+    g = torch.empty((k, 3, mesh.n_elem), dtype=X.dtype, device=X.device) if out is None else out
+    _need(g, "out", X.dtype, shape=(k, 3, mesh.n_elem))
+    check(lib().dgo_face_gradient(mesh.handle, _dtype_code(X.dtype), _ptr(X), k, _ptr(u), _ptr(g),
+                                  _stream()), "dgo_face_gradient")
+    return g
+
+
+def face_divergence(mesh: Mesh, X: torch.Tensor, y: torch.Tensor, out=None):
+    """Divergence D = G^T diag(A) of face fields y ((3, nF) or (k, 3, nF)):
+    an (nV, k) tensor, (nV,) for a (3, nF) input."""
+    _need(X, "X", shape=(mesh.nV, 3))
+    _need(y, "y", X.dtype)
+    k = 1 if y.dim() == 2 else y.shape[0]
+    if tuple(y.shape[-2:]) != (3, mesh.n_elem):
+        raise ValueError("y must be (3, nF) or (k, 3, nF)")
+    d = torch.empty((mesh.nV, k), dtype=X.dtype, device=X.device) if out is None else out
+    _need(d, "out", X.dtype, shape=(mesh.nV, k))
+    check(lib().dgo_face_divergence(mesh.handle, _dtype_code(X.dtype), _ptr(X), k, _ptr(y), _ptr(d),
+                                    _stream()), "dgo_face_divergence")
+    return d[:, 0] if y.dim() == 2 and out is None else d
 
 
 def assemble_vjp(mesh: Mesh, X, gK=None, gM=None):

@@ -82,6 +82,9 @@ SIGNATURES = {
     "dgo_assemble": (C.c_int, [P, C.c_int, i32, P, C.POINTER(AssembleOpts), P, P,
                                C.POINTER(i64), P]),
     "dgo_assemble_vjp": (C.c_int, [P, C.c_int, i32, P, P, P, P, P]),
+    "dgo_assemble_intrinsic": (C.c_int, [P, C.c_int, i32, P, P, P, P, P, P]),
+    "dgo_face_gradient": (C.c_int, [P, C.c_int, P, i32, P, P, P]),
+    "dgo_face_divergence": (C.c_int, [P, C.c_int, P, i32, P, P, P]),
     "dgo_spmv": (C.c_int, [P, C.c_int, i32, f64, P, f64, P, i32, P, P, P]),
     "dgo_pcg": (C.c_int, [P, C.c_int, f64, P, f64, P, P, P, i32, P, P, C.POINTER(CgOpts),
                           C.POINTER(CgReport), P]),

@@ -34,6 +34,21 @@ k_assemble(AsmView v, int32_t nblocks, int64_t nnz, const R *__restrict__ X,
                            Mdiag + bt * (int64_t)v.nV, use_clamp, cmin, n_degenerate, smem);
 }
 
+// Intrinsic variant: the same row blocks with edge lengths as input.
+template <typename R>
+__global__ void __launch_bounds__(kAssembleThreads)
+k_assemble_intrinsic(AsmView v, int32_t nblocks, int64_t nnz, int64_t nE,
+                     const int32_t *__restrict__ inc_elem, const int32_t *__restrict__ elem_edge,
+                     const R *__restrict__ lengths, R *__restrict__ Kvals, R *__restrict__ Mdiag,
+                     int use_clamp, R cmin, int32_t *__restrict__ n_degenerate) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tile = xcd_tile(blockIdx.x, nblocks);
+    const int64_t bt = blockIdx.y;
+    assemble_block<R, 2, true>(v, tile, lengths + bt * nE, Kvals + bt * nnz,
+                               Mdiag + bt * (int64_t)v.nV, use_clamp, cmin, n_degenerate, smem,
+                               inc_elem, elem_edge);
+}
+
 // ------------------------------------------------------------------- VJP
 
 template <typename R>
@@ -311,6 +326,23 @@ dgo_status launch_assemble(const dgo_mesh *m, int32_t batch, const void *X,
     return DGO_OK;
 }
 
+template <typename R>
+dgo_status launch_assemble_intrinsic(const dgo_mesh *m, int32_t batch, const void *lengths,
+                                     const dgo_assemble_opts *o, void *K, void *M, int32_t *ndeg,
+                                     hipStream_t s) {
+    const size_t lds = (size_t)assembly_lds_bytes(2, (int)sizeof(R), m->rpb, m->max_block_nnz,
+                                                  m->max_block_inc);
+    dim3 grid((unsigned)m->nblocks, (unsigned)batch);
+    const int uc = o && o->use_clamp ? 1 : 0;
+    const R cm = o ? (R)o->clamp_min : R(0);
+    DGO_LAUNCH("assemble_intrinsic", s,
+               k_assemble_intrinsic<R><<<grid, kAssembleThreads, lds, s>>>(
+                   view_of(m), m->nblocks, m->nnz, m->nE, m->inc_elem, m->elem_edge,
+                   (const R *)lengths, (R *)K, (R *)M, uc, cm, ndeg));
+    DGO_HIP(hipGetLastError());
+    return DGO_OK;
+}
+
 }  // namespace
 }  // namespace dgo
 
@@ -339,6 +371,40 @@ extern "C" dgo_status dgo_assemble(const dgo_mesh *m, dgo_dtype dtype, int32_t b
         DGO_HIP(hipStreamSynchronize(s));
         *h_n_degenerate = h;
         if (h) return fail(DGO_ERR_DEGENERATE, "dgo_assemble: zero-measure element(s)");
+    }
+    return DGO_OK;
+}
+
+extern "C" dgo_status dgo_assemble_intrinsic(const dgo_mesh *m, dgo_dtype dtype, int32_t batch,
+                                             const void *d_lengths, const dgo_assemble_opts *opts,
+                                             void *d_Kvals, void *d_Mdiag, int64_t *h_n_degenerate,
+                                             dgo_stream stream) {
+    clear_error();
+    if (!m || !d_lengths || !d_Kvals || !d_Mdiag)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_intrinsic: NULL argument");
+    if (dtype != DGO_F32 && dtype != DGO_F64)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_intrinsic: bad dtype");
+    if (batch < 1 || batch > 65535)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_intrinsic: batch must be in [1, 65535]");
+    if (m->dim != 2)
+        return fail(DGO_ERR_UNSUPPORTED, "dgo_assemble_intrinsic: triangle meshes only");
+    hipStream_t s = (hipStream_t)stream;
+    dgo_mesh *mm = const_cast<dgo_mesh *>(m);
+    DGO_TRY(mesh_inc_elem(mm, s));
+    void *ws;
+    DGO_TRY(mesh_workspace(mm, 256, s, &ws));
+    int32_t *ndeg = (int32_t *)ws;
+    k_zero_i32<<<1, 1, 0, s>>>(ndeg);
+    if (dtype == DGO_F64)
+        DGO_TRY(launch_assemble_intrinsic<double>(m, batch, d_lengths, opts, d_Kvals, d_Mdiag, ndeg, s));
+    else
+        DGO_TRY(launch_assemble_intrinsic<float>(m, batch, d_lengths, opts, d_Kvals, d_Mdiag, ndeg, s));
+    if (h_n_degenerate) {
+        int32_t h = 0;
+        DGO_HIP(hipMemcpyAsync(&h, ndeg, sizeof h, hipMemcpyDeviceToHost, s));
+        DGO_HIP(hipStreamSynchronize(s));
+        *h_n_degenerate = h;
+        if (h) return fail(DGO_ERR_DEGENERATE, "dgo_assemble_intrinsic: zero-area triangle(s)");
     }
     return DGO_OK;
 }

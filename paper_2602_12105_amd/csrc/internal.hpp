@@ -116,6 +116,12 @@ struct dgo_mesh {
     int32_t *vjp_mirror = nullptr;   // nnz
     int32_t *vjp_coldiag = nullptr;  // nnz
     int32_t *vjp_opp = nullptr;      // 2 x n_inc
+    // element of each incidence record (built on first use by the kernels
+    // that need the element itself: intrinsic assembly, divergence)
+    int32_t *inc_elem = nullptr;     // n_inc
+    // per incidence record of a triangle mesh: p * n_elem + element, p the
+    // vertex's local position (built on first use by the divergence)
+    int32_t *inc_tslot = nullptr;    // n_inc
 
     // row blocks for the row-centric kernels
     int32_t rpb = 0;            // rows per workgroup
@@ -169,6 +175,9 @@ PcgLayout pcg_layout(int64_t nV, int64_t nvals, int k, size_t elem);
 
 // Grow the mesh workspace to at least `bytes`; contents are not preserved.
 dgo_status mesh_workspace(dgo_mesh *m, size_t bytes, hipStream_t s, void **out);
+
+// Build m->inc_elem if it is not there yet (stream-ordered on s).
+dgo_status mesh_inc_elem(dgo_mesh *m, hipStream_t s);
 
 // Exclusive prefix sum of n int32 values into out[0..n]; out[n] = total.
 // `tmp` must hold scan_tmp_elems(n) int32. in and out may alias.

@@ -173,12 +173,46 @@ struct AsmView {
     int32_t nV, rpb, span_max, inc_max;
 };
 
+// Area of a triangle from its edge lengths: Heron's formula in Kahan's
+// numerically stable arrangement (lengths sorted a >= b >= c). Sorting makes
+// the result independent of the order the lengths are passed in, so every
+// row that needs a triangle's area computes the same bits. Lengths that
+// violate the triangle inequality give 0.
+template <typename R>
+__device__ __forceinline__ R heron_area(R a, R b, R c) {
+    R t;
+    if (a < b) { t = a; a = b; b = t; }
+    if (a < c) { t = a; a = c; c = t; }
+    if (b < c) { t = b; b = c; c = t; }
+    const R q = (a + (b + c)) * (c - (a - b)) * (c + (a - b)) * (a + (b - c));
+    return q > R(0) ? R(0.25) * sqrt(q) : R(0);
+}
+
+// Half-cotangents of a triangle (i, a, b) at b and at a from the lengths li,
+// la, lb of the edges opposite i, a, b (law of cosines over 8 A), and its
+// area. The two squared lengths adjacent to each angle are added first: the
+// sum is commutative, so the rows of both endpoints of an edge form the same
+// bits, provided no product is fused into it (hence no contraction here).
+template <typename R>
+__device__ __forceinline__ void intrinsic_terms(R li, R la, R lb, R &hb, R &ha, R &A) {
+#pragma clang fp contract(off)
+    A = heron_area(li, la, lb);
+    const R si = li * li, sa = la * la, sb = lb * lb, d = R(8) * A;
+    hb = ((si + sa) - sb) / d;
+    ha = ((si + sb) - sa) / d;
+}
+
 // Assemble the row block `tile` of one mesh into Kvals / Mdiag (called by the
-// whole workgroup; smem holds assembly_lds_bytes of the view).
-template <typename R, int DIM>
+// whole workgroup; smem holds assembly_lds_bytes of the view). INTR: X holds
+// the mesh's edge lengths instead of positions (triangles only), and
+// inc_elem / elem_edge give each incidence's triangle and its edges.
+template <typename R, int DIM, bool INTR = false>
 __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restrict__ X,
                                R *__restrict__ Kvals, R *__restrict__ Mdiag, int use_clamp,
-                               R cmin, int32_t *__restrict__ n_degenerate, unsigned char *smem) {
+                               R cmin, int32_t *__restrict__ n_degenerate, unsigned char *smem,
+                               const int32_t *__restrict__ inc_elem = nullptr,
+                               const int32_t *__restrict__ elem_edge = nullptr) {
+    static_assert(!INTR || DIM == 2, "intrinsic assembly is for triangle meshes");
     constexpr int CW = DIM == 2 ? 3 : 4;
     const int32_t *__restrict__ rowptr = v.rowptr;
     const int32_t *__restrict__ col = v.col;
@@ -195,10 +229,11 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
         L.lrp[j] = rowptr[r0 + j] - s0;
         L.lvt[j] = vtptr[r0 + j] - q0;
     }
-    for (int32_t j = t; j < 3 * nrows; j += blockDim.x) {
-        const int32_t r = j / 3, c = j - 3 * r;
-        L.xo[c * rpb + r] = X[3 * (int64_t)r0 + j];
-    }
+    if (!INTR)
+        for (int32_t j = t; j < 3 * nrows; j += blockDim.x) {
+            const int32_t r = j / 3, c = j - 3 * r;
+            L.xo[c * rpb + r] = X[3 * (int64_t)r0 + j];
+        }
     for (int32_t j = t; j < span; j += blockDim.x) {
         const int32_t c = col[s0 + j];
         L.lcol[j] = c;
@@ -213,6 +248,19 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
         const int32_t rr = row_of(L.lvt, nrows, q);
         const int32_t i = r0 + rr, base = L.lrp[rr];
         const int32_t la = base + (int32_t)(rec & 255u), lb = base + (int32_t)((rec >> 8) & 255u);
+        if constexpr (INTR) {
+            // triangle (i, a, b) in cyclic order; edge ids by the rule that
+            // slot j of a triangle is the edge opposite its vertex j
+            const int p = (int)(rec >> 24);
+            const int32_t *fe = elem_edge + 3 * (int64_t)inc_elem[q0 + q];
+            const int pa = p == 2 ? 0 : p + 1, pb = p == 0 ? 2 : p - 1;
+            const R ei = X[fe[p]], ea = X[fe[pa]], eb = X[fe[pb]];  // opposite i, a, b
+            R A;
+            intrinsic_terms(ei, ea, eb, L.c(0, q), L.c(1, q), A);
+            L.c(2, q) = A / R(3);
+            if (A == R(0) && i < L.lcol[la] && i < L.lcol[lb]) ++ndeg;
+            continue;
+        }
         const V3<R> xi = L.own(rr);
         if (DIM == 2) {
             const int32_t a = L.lcol[la], b = L.lcol[lb];

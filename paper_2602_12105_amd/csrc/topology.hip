@@ -621,13 +621,37 @@ static void release(dgo_mesh *m, hipStream_t s) {
     void *ptrs[] = {m->elem, m->EV, m->elem_edge, m->elem_sign, m->rowptr, m->col,
                     m->diag, m->vtptr, m->inc, m->bmask, m->rdesc, m->rlen, m->order,
                     m->ell_col, m->ell_src, m->vjp_mirror, m->vjp_coldiag, m->vjp_opp,
-                    m->ws};
+                    m->inc_elem, m->inc_tslot, m->ws};
     for (void *p : ptrs) m->alloc.put(p, s);
 }
 
 }  // namespace dgo
 
 using namespace dgo;
+
+// The same scatter and per-vertex sort as the topology build, so entry q of
+// inc_elem is the element of incidence record q.
+dgo_status dgo::mesh_inc_elem(dgo_mesh *m, hipStream_t s) {
+    if (m->inc_elem) return DGO_OK;
+    const int64_t ninc = m->n_inc;
+    const int32_t nV = m->nV;
+    int32_t *ie = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)(ninc ? ninc : 1), s);
+    int32_t *cursor = (int32_t *)m->alloc.get(sizeof(int32_t) * ((size_t)nV + 1), s);
+    if (!ie || !cursor) {
+        m->alloc.put(ie, s);
+        m->alloc.put(cursor, s);
+        return fail(DGO_ERR_NOMEM, "mesh: incidence element allocation failed");
+    }
+    DGO_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * ((size_t)nV + 1), s));
+    if (ninc) {
+        k_inc_scatter<<<grid_for(ninc, T), T, 0, s>>>(m->elem, ninc, m->nv_elem, m->vtptr, cursor, ie);
+        k_segment_sort<int32_t><<<grid_for(nV, T), T, 0, s>>>(m->vtptr, ie, nV);
+    }
+    DGO_HIP(hipGetLastError());
+    m->alloc.put(cursor, s);
+    m->inc_elem = ie;
+    return DGO_OK;
+}
 
 dgo_status dgo::mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_t *d_elem,
                             const dgo_allocator *alloc, hipStream_t s, RowsMode rows,
