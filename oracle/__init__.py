@@ -58,6 +58,7 @@ def lib():
             "orc_assemble_intrinsic": [i32, i64, P, P, P, P, P, P],
             "orc_face_gradient": [i32, i64, P, P, i32, P, P],
             "orc_face_divergence": [i32, i64, P, P, i32, P, P],
+            "orc_mass_voronoi": [i32, i64, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -291,3 +292,52 @@ def face_divergence(X, F, y):
     _check(lib().orc_face_divergence(X.shape[0], F.shape[0], _p(F), _p(X), k, _p(y), _p(d)),
            "face_divergence")
     return d
+
+
+def mass_voronoi(X, F):
+    """Mixed-Voronoi lumped mass (nV,) of a triangle mesh."""
+    X, F = _f64(X), _i32(F)
+    M = np.empty(X.shape[0])
+    _check(lib().orc_mass_voronoi(X.shape[0], F.shape[0], _p(F), _p(X), _p(M)), "mass_voronoi")
+    return M
+
+
+def csr_rows(rowptr):
+    """Row index of every CSR slot (the row array of the COO form)."""
+    rowptr = np.asarray(rowptr)
+    return np.repeat(np.arange(rowptr.size - 1, dtype=np.int32), np.diff(rowptr))
+
+
+def conformal_laplacian(F, nV, K, rowptr, col):
+    """Conformal Laplacian L_C of the spectral conformal parameterization
+    (Sec. 7.3), dense (2 nV x 2 nV), unknowns ordered (all x, then all y):
+    L_C = [[K, -S], [S, K]], where the conformal energy of a planar map
+    (x, y) is 1/2 u^T L_C u = E_D - A: E_D = 1/2 (x^T K x + y^T K y) its
+    Dirichlet energy and A = x^T S y its signed area by the shoelace formula
+    over the boundary edges (i -> j in the orientation of their one face):
+    S_ij = 1/2, S_ji = -1/2."""
+    F = np.asarray(F)
+    n = int(nV)
+    Kd = np.zeros((n, n))
+    for i in range(n):
+        for s in range(rowptr[i], rowptr[i + 1]):
+            Kd[i, col[s]] = K[s]
+    count = {}
+    for f in F:
+        for j in range(3):
+            a, b = int(f[(j + 1) % 3]), int(f[(j + 2) % 3])
+            key = (min(a, b), max(a, b))
+            count[key] = count.get(key, 0) + 1
+    S = np.zeros((n, n))
+    for f in F:
+        for j in range(3):
+            a, b = int(f[(j + 1) % 3]), int(f[(j + 2) % 3])
+            if count[(min(a, b), max(a, b))] == 1:
+                S[a, b] += 0.5
+                S[b, a] -= 0.5
+    L = np.zeros((2 * n, 2 * n))
+    L[:n, :n] = Kd
+    L[n:, n:] = Kd
+    L[:n, n:] = -S
+    L[n:, :n] = S
+    return L

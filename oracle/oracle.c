@@ -808,3 +808,40 @@ int orc_face_divergence(int32_t nV, int64_t nF, const int32_t *F, const double *
     }
     return ORC_OK;
 }
+
+int orc_mass_voronoi(int32_t nV, int64_t nF, const int32_t *F, const double *X, double *M) {
+    int st = orc_validate(2, nV, nF, F);
+    if (st) return st;
+    if (!X || !M) return ORC_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < nV; ++i) M[i] = 0.0;
+    for (int64_t t = 0; t < nF; ++t) {
+        const int32_t *v = F + 3 * t;
+        const double *x[3] = {X + 3 * v[0], X + 3 * v[1], X + 3 * v[2]};
+        double A = tri_area(x[0], x[1], x[2]);
+        if (A == 0.0) return ORC_ERR_DEGENERATE;
+        /* the angle at corner j is obtuse when the dot product of its two
+         * edges is negative */
+        int obtuse = -1;
+        for (int j = 0; j < 3; ++j) {
+            double e1[3], e2[3];
+            sub3(x[(j + 1) % 3], x[j], e1);
+            sub3(x[(j + 2) % 3], x[j], e2);
+            if (dot3(e1, e2) < 0.0) obtuse = j;
+        }
+        for (int j = 0; j < 3; ++j) {
+            const double *P = x[j], *Q = x[(j + 1) % 3], *R = x[(j + 2) % 3];
+            double a;
+            if (obtuse < 0) {
+                int deg = 0;
+                double PR[3], PQ[3];
+                sub3(R, P, PR);
+                sub3(Q, P, PQ);
+                a = (dot3(PR, PR) * cot_at(P, R, Q, &deg) + dot3(PQ, PQ) * cot_at(P, Q, R, &deg)) / 8.0;
+            } else {
+                a = obtuse == j ? A / 2.0 : A / 4.0;
+            }
+            M[v[j]] += a;
+        }
+    }
+    return ORC_OK;
+}

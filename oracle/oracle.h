@@ -140,4 +140,11 @@ int orc_face_gradient(int32_t nV, int64_t nF, const int32_t *F, const double *X,
 int orc_face_divergence(int32_t nV, int64_t nF, const int32_t *F, const double *X, int32_t k,
                         const double *y, double *div);
 
+/* Mixed-Voronoi lumped mass of a triangle mesh (the "vertex areas" variant
+ * of the lumped mass, Sec. 7.1 and 7.4; the mixed area of Meyer et al. 2003):
+ * per triangle and corner P with other corners Q, R: if no angle of the
+ * triangle is obtuse, (|PR|^2 cot Q + |PQ|^2 cot R) / 8 (the corner's Voronoi
+ * region); else A/2 for the obtuse corner and A/4 for the other two. */
+int orc_mass_voronoi(int32_t nV, int64_t nF, const int32_t *F, const double *X, double *M);
+
 #endif
