@@ -129,6 +129,12 @@ dgo_status dgo_mesh_edges(const dgo_mesh *mesh, int32_t *d_EV, int32_t *d_elem_e
 dgo_status dgo_mesh_csr(const dgo_mesh *mesh, int32_t *d_rowptr, int32_t *d_col,
                         dgo_stream stream);
 
+/* COO form of the CSR pattern (the coordinate sparse format of Sec. 5.1):
+ * d_row (nnz) receives the row of every CSR slot, d_col (nnz) its column, so
+ * values stored in CSR order (Kvals) are already in this COO order. Either
+ * pointer may be NULL, not both. */
+dgo_status dgo_mesh_coo(const dgo_mesh *mesh, int32_t *d_row, int32_t *d_col, dgo_stream stream);
+
 /* Copy out the boundary-vertex mask: d_mask (nV bytes, 1 = boundary). */
 dgo_status dgo_mesh_boundary(const dgo_mesh *mesh, uint8_t *d_mask, dgo_stream stream);
 
@@ -141,7 +147,17 @@ typedef struct {
      * clamped weights. */
     int32_t use_clamp;
     double clamp_min;
+    /* Lumped mass: 0 = barycentric (A/3 per triangle corner, vol/4 per tet
+     * corner); 1 = mixed Voronoi (the "vertex areas" variant, triangles only:
+     * per corner the Voronoi region (|e_ij|^2 cot k + |e_ik|^2 cot j) / 8 when
+     * the triangle has no obtuse angle, else A/2 at the obtuse corner and A/4
+     * at the others; Meyer et al. 2003). */
+    int32_t mass;
 } dgo_assemble_opts;
+
+/* Edge-weight clamp of the ARAP example (Sec. 4.2): its cotan_weights call
+ * clamps the weights from below at this value. */
+#define DGO_ARAP_CLAMP_MIN 1e-5
 
 /* Assemble the stiffness K and lumped mass M of `batch` meshes that share
  * this topology (the cotangent Laplacian of the ARAP example, Sec. 4.2, and
@@ -189,6 +205,24 @@ dgo_status dgo_assemble_intrinsic(const dgo_mesh *mesh, dgo_dtype dtype, int32_t
                                   const void *d_lengths, const dgo_assemble_opts *opts,
                                   void *d_Kvals, void *d_Mdiag, int64_t *h_n_degenerate,
                                   dgo_stream stream);
+
+/* Conformal Laplacian of the spectral conformal parameterization (Sec. 7.3)
+ * from a stiffness K of this triangle mesh (d_Kvals, nnz, from dgo_assemble
+ * or dgo_assemble_intrinsic): the 2 nV x 2 nV matrix
+ *   L_C = [[K, -S], [S, K]]   (unknowns: all x, then all y),
+ * with 1/2 u^T L_C u = E_D(u) - A(u) the conformal energy of a planar map u:
+ * E_D its Dirichlet energy and A(u) = x^T S y its signed area over the
+ * boundary edges, S_ij = 1/2 and S_ji = -1/2 for a boundary edge running
+ * i -> j in its triangle's orientation. CSR output, columns sorted: row x_i
+ * is K's row i then -S_ij at columns nV + j; row y_i is S_ij at columns j then
+ * K's row i at columns nV + j. d_rowptr2 (2 nV + 1) and d_col2 (nnz2) may be
+ * NULL (the pattern depends on the topology only); d_vals2 (nnz2) in dtype,
+ * nnz2 = 2 nnz + 4 n_bfaces (n_bfaces: boundary edges, dgo_mesh_sizes).
+ * Exact (entries are copies of K or +-1/2). The first call on a mesh caches
+ * the boundary orientation of its CSR slots (nnz bytes + 4 (nV + 1)). */
+dgo_status dgo_conformal_laplacian(const dgo_mesh *mesh, dgo_dtype dtype, const void *d_Kvals,
+                                   int32_t *d_rowptr2, int32_t *d_col2, void *d_vals2,
+                                   dgo_stream stream);
 
 /* ------------------------------------------------ face gradient, divergence */
 

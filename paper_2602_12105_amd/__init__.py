@@ -16,12 +16,13 @@ import ctypes as C
 
 import torch
 
-from ._lib import (DGO_F32, DGO_F64, AssembleOpts, CgOpts, CgReport, DgoError, Sizes, check,
-                   lib)
+from ._lib import (ARAP_CLAMP_MIN, DGO_F32, DGO_F64, AssembleOpts, CgOpts, CgReport, DgoError,
+                   Sizes, check, lib)
 
 __all__ = ["Mesh", "assemble", "assemble_vjp", "spmv", "pcg", "linear_solve_vjp", "AssembleFn",
            "LinearSolveFn", "mcf_step", "DgoError", "library_path", "build", "trace_enable",
-           "trace_read", "trace_reset", "assemble_intrinsic", "face_gradient", "face_divergence"]
+           "trace_read", "trace_reset", "assemble_intrinsic", "face_gradient", "face_divergence",
+           "arap_laplacian", "conformal_laplacian"]
 
 
 def build():
@@ -102,6 +103,13 @@ class Mesh:
         check(lib().dgo_mesh_csr(self._h, _ptr(rowptr), _ptr(col), _stream()), "dgo_mesh_csr")
         return rowptr, col
 
+    def coo(self):
+        """(rows, cols) of the CSR pattern in CSR slot order (COO form)."""
+        rows = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        cols = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        check(lib().dgo_mesh_coo(self._h, _ptr(rows), _ptr(cols), _stream()), "dgo_mesh_coo")
+        return rows, cols
+
     def boundary(self):
         m = torch.empty(self.nV, dtype=torch.uint8, device=self.device)
         check(lib().dgo_mesh_boundary(self._h, _ptr(m), _stream()), "dgo_mesh_boundary")
@@ -128,9 +136,22 @@ def _batched(X, nV, name="X", last=3):
     raise ValueError(f"dgo: {name} must be (nV, {last}) or (batch, nV, {last})")
 
 
+_MASS = {"barycentric": 0, "voronoi": 1}
+
+
+def _assemble_opts(clamp_min, mass):
+    if mass not in _MASS:
+        raise ValueError(f"dgo: mass must be one of {sorted(_MASS)}")
+    if clamp_min is None and mass == "barycentric":
+        return None
+    return C.byref(AssembleOpts(0 if clamp_min is None else 1,
+                                0.0 if clamp_min is None else float(clamp_min), _MASS[mass]))
+
+
 def assemble(mesh: Mesh, X: torch.Tensor, clamp_min=None, check_degenerate=False,
-             out=None):
-    """Cotangent stiffness K (CSR values, PSD) and lumped mass diag M."""
+             out=None, mass="barycentric"):
+    """Cotangent stiffness K (CSR values, PSD) and lumped mass diag M
+    (mass: "barycentric" or "voronoi", the mixed-Voronoi vertex areas)."""
     _need(X, "X")
     b, batched = _batched(X, mesh.nV)
     if not batched:
@@ -141,9 +162,7 @@ def assemble(mesh: Mesh, X: torch.Tensor, clamp_min=None, check_degenerate=False
         M = torch.empty((b, mesh.nV) if batched else (mesh.nV,), dtype=X.dtype, device=X.device)
     else:
         K, M = out
-    opts = None
-    if clamp_min is not None:
-        opts = C.byref(AssembleOpts(1, float(clamp_min)))
+    opts = _assemble_opts(clamp_min, mass)
     nd = C.c_int64(0)
     check(lib().dgo_assemble(mesh.handle, dt, b, _ptr(X), opts, _ptr(K), _ptr(M),
                              C.byref(nd) if check_degenerate else None, _stream()), "dgo_assemble")
@@ -151,7 +170,7 @@ def assemble(mesh: Mesh, X: torch.Tensor, clamp_min=None, check_degenerate=False
 
 
 def assemble_intrinsic(mesh: Mesh, lengths: torch.Tensor, clamp_min=None,
-                       check_degenerate=False, out=None):
+                       check_degenerate=False, out=None, mass="barycentric"):
     """K (CSR values) and lumped M of a triangle mesh from its edge lengths,
     (nE,) or (batch, nE) in the mesh's edge order."""
     _need(lengths, "lengths")
@@ -168,9 +187,7 @@ def assemble_intrinsic(mesh: Mesh, lengths: torch.Tensor, clamp_min=None,
         M = torch.empty((b, mesh.nV) if batched else (mesh.nV,), dtype=ty, device=dev)
     else:
         K, M = out
-    opts = None
-    if clamp_min is not None:
-        opts = C.byref(AssembleOpts(1, float(clamp_min)))
+    opts = _assemble_opts(clamp_min, mass)
     nd = C.c_int64(0)
     check(lib().dgo_assemble_intrinsic(mesh.handle, dt, b, _ptr(lengths), opts, _ptr(K), _ptr(M),
                                        C.byref(nd) if check_degenerate else None, _stream()),
@@ -206,6 +223,30 @@ def face_divergence(mesh: Mesh, X: torch.Tensor, y: torch.Tensor, out=None):
     check(lib().dgo_face_divergence(mesh.handle, _dtype_code(X.dtype), _ptr(X), k, _ptr(y), _ptr(d),
                                     _stream()), "dgo_face_divergence")
     return d[:, 0] if y.dim() == 2 and out is None else d
+
+
+def conformal_laplacian(mesh: Mesh, K: torch.Tensor, pattern=True):
+    """Conformal Laplacian L_C = [[K, -S], [S, K]] of a triangle mesh as CSR
+    (rowptr2, col2, vals2) over 2 nV rows (all x, then all y); with
+    pattern=False only vals2 is returned."""
+    _need(K, "K", shape=(mesh.nnz,))
+    nnz2 = 2 * mesh.nnz + 4 * mesh.n_bfaces
+    vals = torch.empty(nnz2, dtype=K.dtype, device=K.device)
+    rp = col = None
+    if pattern:
+        rp = torch.empty(2 * mesh.nV + 1, dtype=torch.int32, device=K.device)
+        col = torch.empty(nnz2, dtype=torch.int32, device=K.device)
+    check(lib().dgo_conformal_laplacian(mesh.handle, _dtype_code(K.dtype), _ptr(K),
+                                        _ptr(rp) if pattern else None,
+                                        _ptr(col) if pattern else None, _ptr(vals), _stream()),
+          "dgo_conformal_laplacian")
+    return (rp, col, vals) if pattern else vals
+
+
+def arap_laplacian(mesh: Mesh, X: torch.Tensor, clamp_min=ARAP_CLAMP_MIN, out=None):
+    """Cotangent stiffness and mass with the ARAP example's default weight
+    clamp (Sec. 4.2: weights clamped from below at 1e-5)."""
+    return assemble(mesh, X, clamp_min=clamp_min, out=out)
 
 
 def assemble_vjp(mesh: Mesh, X, gK=None, gM=None):

@@ -30,7 +30,10 @@ class Sizes(C.Structure):
 
 
 class AssembleOpts(C.Structure):
-    _fields_ = [("use_clamp", i32), ("clamp_min", f64)]
+    _fields_ = [("use_clamp", i32), ("clamp_min", f64), ("mass", i32)]
+
+
+ARAP_CLAMP_MIN = 1e-5  # DGO_ARAP_CLAMP_MIN
 
 
 class CgOpts(C.Structure):
@@ -84,6 +87,8 @@ SIGNATURES = {
     "dgo_assemble_vjp": (C.c_int, [P, C.c_int, i32, P, P, P, P, P]),
     "dgo_assemble_intrinsic": (C.c_int, [P, C.c_int, i32, P, P, P, P, P, P]),
     "dgo_face_gradient": (C.c_int, [P, C.c_int, P, i32, P, P, P]),
+    "dgo_mesh_coo": (C.c_int, [P, P, P, P]),
+    "dgo_conformal_laplacian": (C.c_int, [P, C.c_int, P, P, P, P, P]),
     "dgo_face_divergence": (C.c_int, [P, C.c_int, P, i32, P, P, P]),
     "dgo_spmv": (C.c_int, [P, C.c_int, i32, f64, P, f64, P, i32, P, P, P]),
     "dgo_pcg": (C.c_int, [P, C.c_int, f64, P, f64, P, P, P, i32, P, P, C.POINTER(CgOpts),

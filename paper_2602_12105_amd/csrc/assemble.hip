@@ -26,12 +26,13 @@ template <typename R, int DIM>
 __global__ void __launch_bounds__(kAssembleThreads)
 k_assemble(AsmView v, int32_t nblocks, int64_t nnz, const R *__restrict__ X,
            R *__restrict__ Kvals, R *__restrict__ Mdiag, int use_clamp, R cmin,
-           int32_t *__restrict__ n_degenerate) {
+           int32_t *__restrict__ n_degenerate, int mass_kind) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tile = xcd_tile(blockIdx.x, nblocks);
     const int64_t bt = blockIdx.y;
     assemble_block<R, DIM>(v, tile, X + bt * 3 * (int64_t)v.nV, Kvals + bt * nnz,
-                           Mdiag + bt * (int64_t)v.nV, use_clamp, cmin, n_degenerate, smem);
+                           Mdiag + bt * (int64_t)v.nV, use_clamp, cmin, n_degenerate, smem,
+                           nullptr, nullptr, mass_kind);
 }
 
 // Intrinsic variant: the same row blocks with edge lengths as input.
@@ -40,13 +41,13 @@ __global__ void __launch_bounds__(kAssembleThreads)
 k_assemble_intrinsic(AsmView v, int32_t nblocks, int64_t nnz, int64_t nE,
                      const int32_t *__restrict__ inc_elem, const int32_t *__restrict__ elem_edge,
                      const R *__restrict__ lengths, R *__restrict__ Kvals, R *__restrict__ Mdiag,
-                     int use_clamp, R cmin, int32_t *__restrict__ n_degenerate) {
+                     int use_clamp, R cmin, int32_t *__restrict__ n_degenerate, int mass_kind) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tile = xcd_tile(blockIdx.x, nblocks);
     const int64_t bt = blockIdx.y;
     assemble_block<R, 2, true>(v, tile, lengths + bt * nE, Kvals + bt * nnz,
                                Mdiag + bt * (int64_t)v.nV, use_clamp, cmin, n_degenerate, smem,
-                               inc_elem, elem_edge);
+                               inc_elem, elem_edge, mass_kind);
 }
 
 // ------------------------------------------------------------------- VJP
@@ -314,14 +315,17 @@ dgo_status launch_assemble(const dgo_mesh *m, int32_t batch, const void *X,
     dim3 grid((unsigned)m->nblocks, (unsigned)batch);
     const int uc = o && o->use_clamp ? 1 : 0;
     const R cm = o ? (R)o->clamp_min : R(0);
+    const int mk = o ? o->mass : 0;
     if (m->dim == 2)
         DGO_LAUNCH("assemble_tri", s,
                    k_assemble<R, 2><<<grid, kAssembleThreads, lds, s>>>(
-                       view_of(m), m->nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg));
+                       view_of(m), m->nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg,
+                       mk));
     else
         DGO_LAUNCH("assemble_tet", s,
                    k_assemble<R, 3><<<grid, kAssembleThreads, lds, s>>>(
-                       view_of(m), m->nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg));
+                       view_of(m), m->nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg,
+                       0));
     DGO_HIP(hipGetLastError());
     return DGO_OK;
 }
@@ -335,10 +339,11 @@ dgo_status launch_assemble_intrinsic(const dgo_mesh *m, int32_t batch, const voi
     dim3 grid((unsigned)m->nblocks, (unsigned)batch);
     const int uc = o && o->use_clamp ? 1 : 0;
     const R cm = o ? (R)o->clamp_min : R(0);
+    const int mk = o ? o->mass : 0;
     DGO_LAUNCH("assemble_intrinsic", s,
                k_assemble_intrinsic<R><<<grid, kAssembleThreads, lds, s>>>(
                    view_of(m), m->nblocks, m->nnz, m->nE, m->inc_elem, m->elem_edge,
-                   (const R *)lengths, (R *)K, (R *)M, uc, cm, ndeg));
+                   (const R *)lengths, (R *)K, (R *)M, uc, cm, ndeg, mk));
     DGO_HIP(hipGetLastError());
     return DGO_OK;
 }
@@ -356,6 +361,10 @@ extern "C" dgo_status dgo_assemble(const dgo_mesh *m, dgo_dtype dtype, int32_t b
         return fail(DGO_ERR_INVALID_ARG, "dgo_assemble: NULL argument");
     if (dtype != DGO_F32 && dtype != DGO_F64) return fail(DGO_ERR_INVALID_ARG, "dgo_assemble: bad dtype");
     if (batch < 1 || batch > 65535) return fail(DGO_ERR_INVALID_ARG, "dgo_assemble: batch must be in [1, 65535]");
+    if (opts && (opts->mass < 0 || opts->mass > 1))
+        return fail(DGO_ERR_INVALID_ARG, "dgo_assemble: mass must be 0 or 1");
+    if (opts && opts->mass == 1 && m->dim != 2)
+        return fail(DGO_ERR_UNSUPPORTED, "dgo_assemble: the mixed-Voronoi mass is for triangle meshes");
     hipStream_t s = (hipStream_t)stream;
     void *ws;
     DGO_TRY(mesh_workspace(const_cast<dgo_mesh *>(m), 256, s, &ws));
@@ -388,6 +397,8 @@ extern "C" dgo_status dgo_assemble_intrinsic(const dgo_mesh *m, dgo_dtype dtype,
         return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_intrinsic: batch must be in [1, 65535]");
     if (m->dim != 2)
         return fail(DGO_ERR_UNSUPPORTED, "dgo_assemble_intrinsic: triangle meshes only");
+    if (opts && (opts->mass < 0 || opts->mass > 1))
+        return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_intrinsic: mass must be 0 or 1");
     hipStream_t s = (hipStream_t)stream;
     dgo_mesh *mm = const_cast<dgo_mesh *>(m);
     DGO_TRY(mesh_inc_elem(mm, s));

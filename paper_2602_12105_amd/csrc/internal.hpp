@@ -122,6 +122,11 @@ struct dgo_mesh {
     // per incidence record of a triangle mesh: p * n_elem + element, p the
     // vertex's local position (built on first use by the divergence)
     int32_t *inc_tslot = nullptr;    // n_inc
+    // conformal Laplacian topology (built on first use): per CSR slot (i, j)
+    // +1 if i -> j is a boundary edge in its triangle's orientation, -1 if
+    // j -> i is, else 0; offsets of each row's boundary entries
+    int8_t *conf_bslot = nullptr;    // nnz
+    int32_t *conf_bptr = nullptr;    // nV + 1
 
     // row blocks for the row-centric kernels
     int32_t rpb = 0;            // rows per workgroup

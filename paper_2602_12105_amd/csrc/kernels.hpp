@@ -193,25 +193,49 @@ __device__ __forceinline__ R heron_area(R a, R b, R c) {
 // area. The two squared lengths adjacent to each angle are added first: the
 // sum is commutative, so the rows of both endpoints of an edge form the same
 // bits, provided no product is fused into it (hence no contraction here).
+// With voronoi, m is the corner's mixed-Voronoi area (the Voronoi region
+// (|e_ia|^2 cot b + |e_ib|^2 cot a) / 8 when no angle is obtuse, else A/2 at
+// the obtuse corner and A/4 at the others); otherwise A/3.
 template <typename R>
-__device__ __forceinline__ void intrinsic_terms(R li, R la, R lb, R &hb, R &ha, R &A) {
+__device__ __forceinline__ void intrinsic_terms(R li, R la, R lb, bool voronoi, R &hb, R &ha,
+                                                R &A, R &m) {
 #pragma clang fp contract(off)
     A = heron_area(li, la, lb);
     const R si = li * li, sa = la * la, sb = lb * lb, d = R(8) * A;
     hb = ((si + sa) - sb) / d;
     ha = ((si + sb) - sa) / d;
+    if (!voronoi)
+        m = A / R(3);
+    else if (si > sa + sb)
+        m = A / R(2);
+    else if (sa > si + sb || sb > si + sa)
+        m = A / R(4);
+    else
+        m = (sb * hb + sa * ha) / R(4);
+}
+
+// Corner mass of vertex i in triangle (i, a, b) for the mixed-Voronoi option,
+// from the edge vectors at i, twice the area nn and the half-cotangents at b
+// and a (hb, ha) with the dot products db, da at those corners.
+template <typename R>
+__device__ __forceinline__ R voronoi_corner(V3<R> eia, V3<R> eib, R nn, R hb, R ha, R db, R da) {
+    if (dot(eia, eib) < R(0)) return nn / R(4);
+    if (da < R(0) || db < R(0)) return nn / R(8);
+    return (dot(eia, eia) * hb + dot(eib, eib) * ha) / R(4);
 }
 
 // Assemble the row block `tile` of one mesh into Kvals / Mdiag (called by the
 // whole workgroup; smem holds assembly_lds_bytes of the view). INTR: X holds
 // the mesh's edge lengths instead of positions (triangles only), and
 // inc_elem / elem_edge give each incidence's triangle and its edges.
+// mass_kind 1: mixed-Voronoi lumped mass of triangles (else barycentric).
 template <typename R, int DIM, bool INTR = false>
 __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restrict__ X,
                                R *__restrict__ Kvals, R *__restrict__ Mdiag, int use_clamp,
                                R cmin, int32_t *__restrict__ n_degenerate, unsigned char *smem,
                                const int32_t *__restrict__ inc_elem = nullptr,
-                               const int32_t *__restrict__ elem_edge = nullptr) {
+                               const int32_t *__restrict__ elem_edge = nullptr,
+                               int mass_kind = 0) {
     static_assert(!INTR || DIM == 2, "intrinsic assembly is for triangle meshes");
     constexpr int CW = DIM == 2 ? 3 : 4;
     const int32_t *__restrict__ rowptr = v.rowptr;
@@ -256,8 +280,7 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             const int pa = p == 2 ? 0 : p + 1, pb = p == 0 ? 2 : p - 1;
             const R ei = X[fe[p]], ea = X[fe[pa]], eb = X[fe[pb]];  // opposite i, a, b
             R A;
-            intrinsic_terms(ei, ea, eb, L.c(0, q), L.c(1, q), A);
-            L.c(2, q) = A / R(3);
+            intrinsic_terms(ei, ea, eb, mass_kind == 1, L.c(0, q), L.c(1, q), A, L.c(2, q));
             if (A == R(0) && i < L.lcol[la] && i < L.lcol[lb]) ++ndeg;
             continue;
         }
@@ -285,7 +308,9 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             const R da = ib ? dot(sub(xi, xa), sub(xb, xa)) : dot(sub(xb, xa), sub(xi, xa));
             L.c(0, q) = db * h;
             L.c(1, q) = da * h;
-            L.c(2, q) = nn / R(6);
+            L.c(2, q) = mass_kind == 1
+                            ? voronoi_corner(sub(xa, xi), sub(xb, xi), nn, db * h, da * h, db, da)
+                            : nn / R(6);
             if (n2 == R(0) && ia && ib) ++ndeg;
         } else {
             const int p = (int)(rec >> 24);

@@ -406,6 +406,6 @@ def test_autograd_loss_gradient_cfg5():
     loss.backward()
     for b in range(B):
         Lo, go = oracle.loss_grad_tri(Xs[b], F, u)
-        assert abs(float(quad[b] + M[b].sum()) - Lo) <= 1e-12 * abs(Lo)
+        assert abs(float((quad[b] + M[b].sum()).detach()) - Lo) <= 1e-12 * abs(Lo)
         g = X.grad[b].cpu().numpy()
         assert np.abs(g - go).max() <= 1e-12 * np.abs(go).max()
