@@ -99,6 +99,34 @@ def grid2d(n: int, jitter: float = 0.0, seed: int = 0):
     return X, F
 
 
+def flat_torus(n: int):
+    """Periodic n x n grid (a flat torus, given intrinsically by its edge
+    lengths): vertex id = i*n + j; cell (i, j) split like grid2d with indices
+    taken mod n. Returns (F int32 (2 n^2, 3), ij int64 (n^2, 2)); the length
+    of an edge (a, b) is h * |wrap(ij[a] - ij[b])| with h = 1/n and each
+    difference wrapped into {-1, 0, 1}.
+    """
+    if n < 3:
+        raise ValueError("flat_torus needs n >= 3")
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    ij = np.stack([i.ravel(), j.ravel()], 1)
+    a = (i * n + j).ravel()
+    b = (((i + 1) % n) * n + j).ravel()
+    c = (((i + 1) % n) * n + (j + 1) % n).ravel()
+    d = (i * n + (j + 1) % n).ravel()
+    F = np.empty((2 * a.size, 3), dtype=np.int32)
+    F[0::2] = np.stack([a, b, c], 1)
+    F[1::2] = np.stack([a, c, d], 1)
+    return F, ij
+
+
+def flat_torus_lengths(n: int, ij: np.ndarray, EV: np.ndarray) -> np.ndarray:
+    """Edge lengths of flat_torus(n) for the edge list EV (nE x 2)."""
+    dd = ij[EV[:, 0]] - ij[EV[:, 1]]
+    dd = (dd + 1) % n - 1  # wrap into {-1, 0, 1}
+    return np.sqrt((dd.astype(np.float64) ** 2).sum(axis=1)) / n
+
+
 _PHI = (1.0 + math.sqrt(5.0)) / 2.0
 _ICO_V = np.array([
     [-1, _PHI, 0], [1, _PHI, 0], [-1, -_PHI, 0], [1, -_PHI, 0],

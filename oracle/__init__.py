@@ -341,3 +341,44 @@ def conformal_laplacian(F, nV, K, rowptr, col):
     L[:n, n:] = -S
     L[n:, :n] = S
     return L
+
+
+def canonical_sign(U):
+    """Flip each column so that its entry of largest magnitude (the first
+    such entry on ties) is positive: the canonical sign of the orthonormalized
+    eigenvector blocks of Sec. 5.2 (Eq. eigiter)."""
+    U = np.array(U, dtype=np.float64, copy=True)
+    idx = np.argmax(np.abs(U), axis=0)
+    s = np.sign(U[idx, np.arange(U.shape[1])])
+    s[s == 0] = 1.0
+    return U * s
+
+
+def eigs_smallest(rowptr, col, K, M, k, dense_max=4000, sigma=-1e-3):
+    """The k smallest eigenpairs of the generalized problem K u = lam M u
+    (Sec. 5.2, spectral implicit layers: A U = B U diag(lam), U^T B U = I,
+    with A = K and B = M diagonal and positive). Up to dense_max vertices the
+    definition is evaluated directly: a dense symmetric eigendecomposition of
+    M^-1/2 K M^-1/2 (LAPACK through numpy); above, ARPACK in shift-invert
+    mode about sigma (scipy eigsh; the CPU eigensolver the paper names).
+    Returns (lam ascending (k,), U (nV, k) M-orthonormal with canonical signs)."""
+    import scipy.sparse as sps
+    rowptr, col = np.asarray(rowptr), np.asarray(col)
+    K, M = np.asarray(K, np.float64), np.asarray(M, np.float64)
+    n = rowptr.size - 1
+    A = sps.csr_matrix((K, col, rowptr), shape=(n, n))
+    if n <= dense_max:
+        d = 1.0 / np.sqrt(M)
+        S = (A.toarray() * d[:, None]) * d[None, :]
+        S = 0.5 * (S + S.T)
+        lam, V = np.linalg.eigh(S)
+        lam, V = lam[:k], V[:, :k] * d[:, None]
+    else:
+        from scipy.sparse.linalg import eigsh
+        lam, V = eigsh(A.tocsc(), k=k, M=sps.diags(M).tocsc(), sigma=sigma, which="LM", tol=1e-14)
+        o = np.argsort(lam)
+        lam, V = lam[o], V[:, o]
+    # M-normalize (eigsh and eigh both return B-orthonormal vectors up to
+    # rounding; normalize again so the comparison metric is exact)
+    V = V / np.sqrt(np.einsum("ij,i,ij->j", V, M, V))[None, :]
+    return lam, canonical_sign(V)
