@@ -444,6 +444,25 @@ def suite(args, dgo, torch, meshgen):
                           "forward_ms": float(np.median(fw)), "backward_ms": float(np.median(bw))}
     del m, W, Xd, Xg, u, loss
 
+    # spectral layer forward (Sec. 5.2): the 9 smallest eigenpairs of the
+    # icosphere L7 Laplacian (0, the l = 1 and l = 2 clusters) to 1e-8
+    log(args, "suite: eigenpairs L7")
+    X, F = meshgen.icosphere(args.level, 1e-3, 0)
+    m = dgo.Mesh(torch.from_numpy(F).to(dev), X.shape[0])
+    K, M = dgo.assemble(m, torch.from_numpy(X).to(dev, td))
+    times = []
+    for r in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, U, rep = dgo.eigs_smallest(m, M, K, 9)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    out["eigs_L7"] = {"nV": m.nV, "k": 9, "block": rep["block"], "sigma": rep["sigma"],
+                      "outer_iters": rep["iters"], "inner_pcg_iters": rep["inner_iters"],
+                      "converged": rep["converged"], "max_resid": max(rep["resid"]),
+                      "ms": float(np.median(times)), "lambda": [float(v) for v in lam]}
+    del m, K, M, U
+
     # size sweep past the 256 MB last-level cache: icosphere L8 and L9
     for L in (8, 9):
         log(args, f"suite: icosphere L{L}")

@@ -316,6 +316,49 @@ dgo_status dgo_linear_solve_vjp(const dgo_mesh *mesh, dgo_dtype dtype, double al
                                 int32_t k, const void *d_lambda, const void *d_u, const void *d_f,
                                 void *d_gK, void *d_gM, dgo_stream stream);
 
+/* ------------------------------------------------------------ eigenpairs */
+
+typedef struct {
+    double sigma;           /* shift, < 0; 0 selects -1 / sum(M) (minus the
+                               reciprocal of the total measure) */
+    double tol;             /* stop when every requested pair has
+                               ||K u - lam M u||_{M^-1} <= tol max(|lam|, |sigma|)
+                               with u^T M u = 1 (0: 1e-8 FP64, 1e-4 FP32) */
+    double inner_rtol;      /* PCG rtol of each inner solve (0: tol / 10) */
+    int32_t block;          /* subspace size p, k <= p <= 64 (0: min(64, nV,
+                               max(2k, k + 8))) */
+    int32_t max_iter;       /* outer iterations (0: 200) */
+    int32_t inner_max_iter; /* PCG iteration cap per solve (0: 20000) */
+    int32_t reserved;
+    uint64_t seed;          /* start block: splitmix64 stream from this seed */
+} dgo_eig_opts;
+
+typedef struct {
+    int32_t k, block;
+    int32_t iters;          /* outer iterations (solves) performed */
+    int32_t converged;      /* 1 if every requested pair met tol */
+    int64_t inner_iters;    /* PCG iterations summed over the solves (the
+                               longest column of each) */
+    double sigma;           /* shift used */
+    double resid[64];       /* relative residual of each requested pair */
+} dgo_eig_report;
+
+/* The k smallest eigenpairs of K u = lam M u (the forward pass of the
+ * spectral implicit layers, Sec. 5.2: A U = B U diag(lam), U^T B U = I with
+ * A = K, B = M diagonal positive): subspace iteration on (K - sigma M)^-1 M
+ * with Rayleigh-Ritz, the fixed point U = Q((A - sigma B)^-1 B U) of
+ * Eq. eigiter, each inverse applied by dgo_pcg to all p columns. d_Mdiag
+ * (nV), d_Kvals (nnz) in dtype; d_U (nV x k, row-major) receives the
+ * M-orthonormal eigenvectors, each column signed so that its entry of
+ * largest magnitude (the first on ties) is positive; h_lambda (k, host)
+ * the eigenvalues ascending. 1 <= k <= min(64, nV). Synchronises the stream
+ * once per outer iteration; deterministic. Returns DGO_ERR_NOT_CONVERGED
+ * only if the iterated block loses rank; otherwise non-convergence is
+ * reported in h_rep (may be NULL). opts may be NULL (defaults). */
+dgo_status dgo_eigs_smallest(const dgo_mesh *mesh, dgo_dtype dtype, const void *d_Mdiag,
+                             const void *d_Kvals, int32_t k, const dgo_eig_opts *opts, void *d_U,
+                             double *h_lambda, dgo_eig_report *h_rep, dgo_stream stream);
+
 /* ----------------------------------------------------------------- tracing */
 
 /* Kernel timing for measurement (not part of the method). While enabled,

@@ -17,12 +17,12 @@ import ctypes as C
 import torch
 
 from ._lib import (ARAP_CLAMP_MIN, DGO_F32, DGO_F64, AssembleOpts, CgOpts, CgReport, DgoError,
-                   Sizes, check, lib)
+                   EigOpts, EigReport, Sizes, check, lib)
 
 __all__ = ["Mesh", "assemble", "assemble_vjp", "spmv", "pcg", "linear_solve_vjp", "AssembleFn",
            "LinearSolveFn", "mcf_step", "DgoError", "library_path", "build", "trace_enable",
            "trace_read", "trace_reset", "assemble_intrinsic", "face_gradient", "face_divergence",
-           "arap_laplacian", "conformal_laplacian"]
+           "arap_laplacian", "conformal_laplacian", "eigs_smallest"]
 
 
 def build():
@@ -241,6 +241,26 @@ def conformal_laplacian(mesh: Mesh, K: torch.Tensor, pattern=True):
                                         _ptr(col) if pattern else None, _ptr(vals), _stream()),
           "dgo_conformal_laplacian")
     return (rp, col, vals) if pattern else vals
+
+
+def eigs_smallest(mesh: Mesh, M: torch.Tensor, K: torch.Tensor, k: int, sigma=0.0, tol=0.0,
+                  block=0, max_iter=0, inner_rtol=0.0, inner_max_iter=0, seed=0):
+    """The k smallest eigenpairs of K u = lam M u (spectral implicit layer
+    forward): returns (lam (k,) float64 on the host, U (nV, k) M-orthonormal
+    with canonical signs, report dict). sigma = 0 picks -1 / sum(M)."""
+    _need(M, "M", shape=(mesh.nV,))
+    _need(K, "K", M.dtype, shape=(mesh.nnz,))
+    U = torch.empty((mesh.nV, k), dtype=M.dtype, device=M.device)
+    lam = (C.c_double * k)()
+    o = EigOpts(float(sigma), float(tol), float(inner_rtol), int(block), int(max_iter),
+                int(inner_max_iter), 0, int(seed))
+    r = EigReport()
+    check(lib().dgo_eigs_smallest(mesh.handle, _dtype_code(M.dtype), _ptr(M), _ptr(K), int(k),
+                                  C.byref(o), _ptr(U), lam, C.byref(r), _stream()),
+          "dgo_eigs_smallest")
+    rep = {"k": r.k, "block": r.block, "iters": r.iters, "converged": bool(r.converged),
+           "inner_iters": r.inner_iters, "sigma": r.sigma, "resid": list(r.resid[:k])}
+    return torch.tensor(list(lam), dtype=torch.float64), U, rep
 
 
 def arap_laplacian(mesh: Mesh, X: torch.Tensor, clamp_min=ARAP_CLAMP_MIN, out=None):

@@ -36,6 +36,17 @@ class AssembleOpts(C.Structure):
 ARAP_CLAMP_MIN = 1e-5  # DGO_ARAP_CLAMP_MIN
 
 
+class EigOpts(C.Structure):
+    _fields_ = [("sigma", f64), ("tol", f64), ("inner_rtol", f64), ("block", i32),
+                ("max_iter", i32), ("inner_max_iter", i32), ("reserved", i32),
+                ("seed", C.c_uint64)]
+
+
+class EigReport(C.Structure):
+    _fields_ = [("k", i32), ("block", i32), ("iters", i32), ("converged", i32),
+                ("inner_iters", C.c_int64), ("sigma", f64), ("resid", f64 * 64)]
+
+
 class CgOpts(C.Structure):
     _fields_ = [("rtol", f64), ("max_iter", i32), ("fixed_iters", i32), ("check_every", i32),
                 ("stall_iters", i32), ("strict", i32)]
@@ -88,6 +99,7 @@ SIGNATURES = {
     "dgo_assemble_intrinsic": (C.c_int, [P, C.c_int, i32, P, P, P, P, P, P]),
     "dgo_face_gradient": (C.c_int, [P, C.c_int, P, i32, P, P, P]),
     "dgo_mesh_coo": (C.c_int, [P, P, P, P]),
+    "dgo_eigs_smallest": (C.c_int, [P, C.c_int, P, P, i32, P, P, P, P, P]),
     "dgo_conformal_laplacian": (C.c_int, [P, C.c_int, P, P, P, P, P]),
     "dgo_face_divergence": (C.c_int, [P, C.c_int, P, i32, P, P, P]),
     "dgo_spmv": (C.c_int, [P, C.c_int, i32, f64, P, f64, P, i32, P, P, P]),
