@@ -189,7 +189,7 @@ dgo_status dgo_assemble_vjp(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch
                             dgo_stream stream);
 
 /* Intrinsic assembly (the intrinsic cotangent weights of the SCP example,
- * Sec. 7.3): K and M of a triangle mesh from its edge lengths alone. For a
+ * Sec. 7.2): K and M of a triangle mesh from its edge lengths alone. For a
  * triangle with edge lengths l_j (edge opposite local vertex j) and area A
  * (Heron's formula in Kahan's stable form), the weight of the angle at vertex
  * j is 1/2 cot = (l_{j+1}^2 + l_{j+2}^2 - l_j^2) / (8 A); K and M then follow
@@ -206,7 +206,7 @@ dgo_status dgo_assemble_intrinsic(const dgo_mesh *mesh, dgo_dtype dtype, int32_t
                                   void *d_Kvals, void *d_Mdiag, int64_t *h_n_degenerate,
                                   dgo_stream stream);
 
-/* Conformal Laplacian of the spectral conformal parameterization (Sec. 7.3)
+/* Conformal Laplacian of the spectral conformal parameterization (Sec. 7.2)
  * from a stiffness K of this triangle mesh (d_Kvals, nnz, from dgo_assemble
  * or dgo_assemble_intrinsic): the 2 nV x 2 nV matrix
  *   L_C = [[K, -S], [S, K]]   (unknowns: all x, then all y),

@@ -310,7 +310,7 @@ def csr_rows(rowptr):
 
 def conformal_laplacian(F, nV, K, rowptr, col):
     """Conformal Laplacian L_C of the spectral conformal parameterization
-    (Sec. 7.3), dense (2 nV x 2 nV), unknowns ordered (all x, then all y):
+    (Sec. 7.2), dense (2 nV x 2 nV), unknowns ordered (all x, then all y):
     L_C = [[K, -S], [S, K]], where the conformal energy of a planar map
     (x, y) is 1/2 u^T L_C u = E_D - A: E_D = 1/2 (x^T K x + y^T K y) its
     Dirichlet energy and A = x^T S y its signed area by the shoelace formula

@@ -112,7 +112,7 @@ int orc_linear_solve_vjp(int32_t nV, const int32_t *rowptr, const int32_t *col, 
                          double beta, int32_t k, const double *lambda, const double *u,
                          const double *f, double *gK, double *gM);
 
-/* Intrinsic assembly (Sec. 7.3, the intrinsic cotangent weights of the SCP
+/* Intrinsic assembly (Sec. 7.2, the intrinsic cotangent weights of the SCP
  * example): K and M of a triangle mesh from its edge lengths alone. lengths
  * is indexed like EV (the sorted (min, max) edges of orc_edges). For a
  * triangle with edge lengths l_j (edge opposite local vertex j) and area A

@@ -1,6 +1,6 @@
 // Operator variants on the mesh's CSR pattern: the COO form of the pattern
 // and the conformal Laplacian of the spectral conformal parameterization
-// (Sec. 7.3).
+// (Sec. 7.2).
 //
 // Conformal Laplacian: for a map u = (x, y) of the mesh into the plane, the
 // conformal energy E_D - A is 1/2 u^T L_C u with L_C = [[K, -S], [S, K]]
