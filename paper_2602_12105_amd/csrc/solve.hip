@@ -344,6 +344,23 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
     __shared__ int s_any;
     const int t = threadIdx.x;
     const CgCol *sin = reduce ? st_prev : st_cur;
+    // The first tile's vectors do not depend on alpha and beta: their loads
+    // are issued before the reduction below, which they overlap.
+    const VLane L = vlane(k, KP);
+    int64_t t0, t1;
+    tile_range(((int64_t)nV + L.gpb - 1) / L.gpb, t0, t1);
+    const int64_t i0 = t0 * L.gpb + L.grp;
+    const bool pre = L.act && t0 < t1 && i0 < nV;
+    R fr = 0, fw = 0, fp = 0, fs = 0, fx = 0, fd = 0;
+    if (pre) {
+        const int64_t e = i0 * k + L.c;
+        fr = r[e];
+        fw = w[e];
+        fp = p[e];
+        fs = sv[e];
+        fx = x[e];
+        fd = invD[i0];
+    }
     if (t == 0) {
         int any = 0;
         for (int c = 0; c < k; ++c) any |= sin[c].active;
@@ -366,18 +383,17 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
         s_ab[k + t] = c.beta;
     }
     __syncthreads();
-    const VLane L = vlane(k, KP);
     const bool on = L.act && s_on[L.c];
     const R a = on ? (R)s_ab[L.c] : R(0), bt = on ? (R)s_ab[k + L.c] : R(0);
     double d[2] = {0.0, 0.0};
-    int64_t t0, t1;
-    tile_range(((int64_t)nV + L.gpb - 1) / L.gpb, t0, t1);
     if (on) {
         for (int64_t tile = t0; tile < t1; ++tile) {
             const int64_t i = tile * L.gpb + L.grp;
             if (i >= nV) continue;
             const int64_t e = i * k + L.c;
-            const R rv = r[e], wv = w[e], pv = p[e], s0 = sv[e], xv = x[e], dv = invD[i];
+            const bool first = tile == t0;
+            const R rv = first ? fr : r[e], wv = first ? fw : w[e], pv = first ? fp : p[e],
+                    s0 = first ? fs : sv[e], xv = first ? fx : x[e], dv = first ? fd : invD[i];
             const R pn = dv * rv + bt * pv;
             const R sn = wv + bt * s0;
             const R rn = rv - a * sn;
@@ -651,7 +667,7 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     prm.stall = o.stall_iters;
     prm.k = k;
 
-    const unsigned nb_v = nblocks_for(ntiles(nV, TR / KP), kMaxRedBlocks);
+    const unsigned nb_v = nblocks_for(ntiles(nV, TR / KP), 256);
     const R ra = (R)alpha, rb = (R)beta;
 
     DGO_LAUNCH("cg_invdiag", s,
