@@ -697,25 +697,24 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
 
     const int every = o.fixed_iters ? (o.max_iter > 0 ? o.max_iter : 1)
                                     : (o.check_every > 0 ? o.check_every : 8);
-    // Iterations i0 .. i0 + count - 1, then a finalize that leaves the state
-    // of iteration i0 + count for the host. Each iteration is two kernels:
-    // the vector update (which also finishes the previous iteration's
-    // reductions, except in the first iteration of a chunk, whose state the
-    // finalize before it computed) and w = A z with w.z.
+    // Iterations i0 .. i0 + count - 1. Each iteration is two kernels: the
+    // vector update (which also finishes the previous iteration's reductions
+    // and writes the state of iteration i to stt[i & 1]) and w = A z with w.z.
+    // After iteration e - 1 the newest complete state is stt[(e - 1) & 1]: it
+    // carries the stopping tests of every iteration but the last, which the
+    // host's progress check may therefore see one iteration late; a single
+    // finalize after the last iteration completes the state.
+    int nbs = nb_s;
     auto iterate = [&](hipStream_t st_s, int32_t i0, int32_t count) {
-        int nbs = nb_s;
         for (int32_t it = 0; it < count; ++it) {
             const int32_t i = i0 + it;
             DGO_LAUNCH("cg_vupdate", st_s,
                        k_cg_vupdate<R><<<nb_v, TR, 0, st_s>>>(
                            (int32_t)nV, k, KP, x, r, p, sv, w, dvec, stt[(i + 1) & 1], stt[i & 1],
-                           it > 0 ? 1 : 0, partU[i & 1], (int)nb_v, part2, nbs, partU[(i + 1) & 1],
+                           i > 0 ? 1 : 0, partU[i & 1], (int)nb_v, part2, nbs, partU[(i + 1) & 1],
                            prm));
             nbs = launch_sdot<R>(m, v, dvec, k, r, w, stt[i & 1], part2, st_s);
         }
-        const int32_t e = i0 + count;
-        launch_fin<FIN_SR_ITER>(partU[e & 1], (int)nb_v, part2, nbs, k, stt[(e + 1) & 1], stt[e & 1],
-                                prm, nullptr, st_s);
     };
     // Progress polling without idling the device: chunk n + 1 is queued
     // before the host waits for the state copied after chunk n, so the
@@ -736,7 +735,7 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
             cur = prev == 0 ? 1 : 0;
             iterate(s, done_iters, chunk);
             done_iters += chunk;
-            DGO_HIP(hipMemcpyAsync(hpoll + cur * kMaxK, stt[done_iters & 1], sizeof(CgCol) * k,
+            DGO_HIP(hipMemcpyAsync(hpoll + cur * kMaxK, stt[(done_iters - 1) & 1], sizeof(CgCol) * k,
                                    hipMemcpyDeviceToHost, s));
             DGO_HIP(hipEventRecord(mm->poll_ev[cur], s));
             DGO_HIP(hipGetLastError());
@@ -750,6 +749,9 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
         if (cur < 0) break;
         prev = cur;
     }
+    if (done_iters > 0)
+        launch_fin<FIN_SR_ITER>(partU[done_iters & 1], (int)nb_v, part2, nbs, k,
+                                stt[(done_iters + 1) & 1], stt[done_iters & 1], prm, nullptr, s);
     CgCol hst[kMaxK];
     if (ell)
         DGO_LAUNCH("cg_unorder", s,
