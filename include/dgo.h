@@ -270,6 +270,9 @@ typedef struct {
     int32_t strict;       /* != 0: return DGO_ERR_NOT_CONVERGED if a column
                              stops without meeting rtol (the paper's strict
                              flag of its GMRES, Sec. 6.2) */
+    double rtol_initial;  /* > 0: a column also stops (and counts as
+                             converged) when ||r||_2 <= rtol_initial ||r_0||_2,
+                             r_0 the residual of the initial guess; 0: off */
 } dgo_cg_opts;
 
 typedef struct {
@@ -325,6 +328,8 @@ typedef struct {
                                ||K u - lam M u||_{M^-1} <= tol max(|lam|, |sigma|)
                                with u^T M u = 1 (0: 1e-8 FP64, 1e-4 FP32) */
     double inner_rtol;      /* PCG rtol of each inner solve (0: tol / 10) */
+    double inner_rtol_initial; /* each inner solve also stops at this fraction
+                               of its warm start's residual (0: 0.1; < 0: off) */
     int32_t block;          /* subspace size p, k <= p <= 64 (0: min(64, nV,
                                max(2k, k + 8))) */
     int32_t max_iter;       /* outer iterations (0: 200) */

@@ -244,7 +244,8 @@ def conformal_laplacian(mesh: Mesh, K: torch.Tensor, pattern=True):
 
 
 def eigs_smallest(mesh: Mesh, M: torch.Tensor, K: torch.Tensor, k: int, sigma=0.0, tol=0.0,
-                  block=0, max_iter=0, inner_rtol=0.0, inner_max_iter=0, seed=0):
+                  block=0, max_iter=0, inner_rtol=0.0, inner_max_iter=0, seed=0,
+                  inner_rtol_initial=0.0):
     """The k smallest eigenpairs of K u = lam M u (spectral implicit layer
     forward): returns (lam (k,) float64 on the host, U (nV, k) M-orthonormal
     with canonical signs, report dict). sigma = 0 picks -1 / sum(M)."""
@@ -252,8 +253,8 @@ def eigs_smallest(mesh: Mesh, M: torch.Tensor, K: torch.Tensor, k: int, sigma=0.
     _need(K, "K", M.dtype, shape=(mesh.nnz,))
     U = torch.empty((mesh.nV, k), dtype=M.dtype, device=M.device)
     lam = (C.c_double * k)()
-    o = EigOpts(float(sigma), float(tol), float(inner_rtol), int(block), int(max_iter),
-                int(inner_max_iter), 0, int(seed))
+    o = EigOpts(float(sigma), float(tol), float(inner_rtol), float(inner_rtol_initial), int(block),
+                int(max_iter), int(inner_max_iter), 0, int(seed))
     r = EigReport()
     check(lib().dgo_eigs_smallest(mesh.handle, _dtype_code(M.dtype), _ptr(M), _ptr(K), int(k),
                                   C.byref(o), _ptr(U), lam, C.byref(r), _stream()),
@@ -301,8 +302,10 @@ def spmv(mesh: Mesh, alpha, M, beta, K, x, out=None):
 
 
 def pcg(mesh: Mesh, alpha, M, beta, K, b, u0=None, mask=None, g=None, rtol=1e-8,
-        max_iter=1000, fixed_iters=False, check_every=8, stall_iters=0, strict=False):
-    """Jacobi PCG on (alpha M + beta K) u = b; returns (u, report dict)."""
+        max_iter=1000, fixed_iters=False, check_every=8, stall_iters=0, strict=False,
+        rtol_initial=0.0):
+    """Jacobi PCG on (alpha M + beta K) u = b; returns (u, report dict).
+    rtol_initial > 0 also stops a column at that fraction of its initial residual."""
     _need(M, "M")
     _need(K, "K", M.dtype)
     _need(b, "b", M.dtype)
@@ -312,7 +315,7 @@ def pcg(mesh: Mesh, alpha, M, beta, K, b, u0=None, mask=None, g=None, rtol=1e-8,
         _need(mask, "mask", torch.uint8)
         _need(g, "g", M.dtype, b.shape)
     opts = CgOpts(float(rtol), int(max_iter), int(bool(fixed_iters)), int(check_every),
-                  int(stall_iters), int(bool(strict)))
+                  int(stall_iters), int(bool(strict)), float(rtol_initial))
     rep = CgReport()
     check(lib().dgo_pcg(mesh.handle, _dtype_code(M.dtype), float(alpha), _ptr(M), float(beta),
                         _ptr(K), _ptr(mask), _ptr(g), k, _ptr(b), _ptr(u), C.byref(opts),

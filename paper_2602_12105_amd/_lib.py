@@ -37,7 +37,8 @@ ARAP_CLAMP_MIN = 1e-5  # DGO_ARAP_CLAMP_MIN
 
 
 class EigOpts(C.Structure):
-    _fields_ = [("sigma", f64), ("tol", f64), ("inner_rtol", f64), ("block", i32),
+    _fields_ = [("sigma", f64), ("tol", f64), ("inner_rtol", f64), ("inner_rtol_initial", f64),
+                ("block", i32),
                 ("max_iter", i32), ("inner_max_iter", i32), ("reserved", i32),
                 ("seed", C.c_uint64)]
 
@@ -49,7 +50,7 @@ class EigReport(C.Structure):
 
 class CgOpts(C.Structure):
     _fields_ = [("rtol", f64), ("max_iter", i32), ("fixed_iters", i32), ("check_every", i32),
-                ("stall_iters", i32), ("strict", i32)]
+                ("stall_iters", i32), ("strict", i32), ("rtol_initial", f64)]
 
 
 class CgReport(C.Structure):

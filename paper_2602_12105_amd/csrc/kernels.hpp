@@ -17,13 +17,13 @@ constexpr int kFinThreads = 1024;
 constexpr int kVecUnroll = 1;     // rows per thread per step in the vector kernels (measured best)
 
 struct CgCol {
-    double rz, pq, alpha, beta, rr, bb, best;
+    double rz, pq, alpha, beta, rr, bb, best, rr0;
     int32_t iters, since, active, converged;
     int32_t stalled, pad0;
 };
 
 struct CgParams {
-    double rtol;
+    double rtol, rtol0;  // stop at rtol ||b_eff|| or (rtol0 > 0) rtol0 ||r_0||
     int32_t max_iter, fixed, stall;
     int32_t k;
 };
@@ -683,7 +683,8 @@ __device__ inline void cg_stop_tests(CgCol &s, double rr, const CgParams &prm) {
     } else {
         s.since += 1;
     }
-    if (!prm.fixed && sqrt(rr) <= prm.rtol * sqrt(s.bb)) {
+    if (!prm.fixed && (sqrt(rr) <= prm.rtol * sqrt(s.bb) ||
+                       (prm.rtol0 > 0.0 && sqrt(rr) <= prm.rtol0 * sqrt(s.rr0)))) {
         s.converged = 1;
         s.active = 0;
     } else if (s.iters >= prm.max_iter) {
@@ -705,6 +706,7 @@ __device__ inline void cg_state_update(int mode, CgCol &s, const double *tot, in
         s.rz = tot[c];
         s.rr = tot[k + c];
         s.bb = tot[2 * k + c];
+        s.rr0 = tot[k + c];
         s.best = s.rr;
         s.iters = 0;
         s.since = 0;
@@ -743,6 +745,7 @@ __device__ inline void cg_sr_update(int mode, CgCol &s, const double *tot, const
     const double g = tot[c], rr = tot[k + c], dl = tot2[c];
     if (mode == FIN_SR_INIT) {
         s.bb = tot[2 * k + c];
+        s.rr0 = tot[k + c];
         s.rr = rr;
         s.best = rr;
         s.iters = 0;

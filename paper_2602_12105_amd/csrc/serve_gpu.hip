@@ -553,6 +553,7 @@ class GpuExec {
         const R a = (R)o_.alpha, b = (R)o_.beta;
         CgParams prm;
         prm.rtol = 0.0;
+        prm.rtol0 = 0.0;
         prm.max_iter = o_.cg_iters;
         prm.fixed = 1;
         prm.stall = 0;

@@ -662,6 +662,7 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
 
     CgParams prm;
     prm.rtol = o.rtol;
+    prm.rtol0 = o.rtol_initial;
     prm.max_iter = o.max_iter;
     prm.fixed = o.fixed_iters;
     prm.stall = o.stall_iters;
@@ -835,8 +836,10 @@ extern "C" dgo_status dgo_pcg(const dgo_mesh *m, dgo_dtype dtype, double alpha, 
         o.check_every = 8;
         o.stall_iters = 0;
         o.strict = 0;
+        o.rtol_initial = 0.0;
     }
-    if (o.max_iter < 0 || !(o.rtol >= 0.0)) return fail(DGO_ERR_INVALID_ARG, "dgo_pcg: bad options");
+    if (o.max_iter < 0 || !(o.rtol >= 0.0) || !(o.rtol_initial >= 0.0))
+        return fail(DGO_ERR_INVALID_ARG, "dgo_pcg: bad options");
     hipStream_t s = (hipStream_t)stream;
     if (dtype == DGO_F64)
         return run_pcg<double>(m, alpha, (const double *)d_Mdiag, beta, (const double *)d_Kvals,
