@@ -18,6 +18,7 @@ constexpr int kVecUnroll = 1;     // rows per thread per step in the vector kern
 
 struct CgCol {
     double rz, pq, alpha, beta, rr, bb, best, rr0;
+    double alpha_prev;  // the step length of the column's previous update
     int32_t iters, since, active, converged;
     int32_t stalled, pad0;
 };
@@ -757,10 +758,12 @@ __device__ inline void cg_sr_update(int mode, CgCol &s, const double *tot, const
         s.rz = g;
         s.pq = dl;
         s.beta = 0.0;
+        s.alpha_prev = 0.0;
         s.alpha = (s.active && dl != 0.0) ? g / dl : 0.0;
         return;
     }
     if (!s.active) return;
+    s.alpha_prev = s.alpha;
     s.iters += 1;
     s.rr = rr;
     cg_stop_tests(s, rr, prm);

@@ -17,18 +17,23 @@
 // one-reduction arrangement of Chronopoulos and Gear: the recurrence s = A p
 // is carried along, so that the three dots an iteration needs (r.z, r.r of the
 // new residual and w.z with w = A z) belong to one residual and are reduced
-// together. An iteration is three kernels:
-//   1. vector update p = z + beta p, s = w + beta s, x += alpha p,
-//      r -= alpha s, with partial sums of r.z and r.r (z = D^-1 r);
+// together. An iteration is two kernels:
+//   1. vector update: every workgroup first adds the previous iteration's
+//      partial sums in the same fixed order and advances the per-column state
+//      (beta, alpha, stopping tests), then p = z + beta p, s = w + beta s,
+//      r -= alpha s, with partial sums of r.z and r.r (z = D^-1 r); x takes
+//      the steps of two iterations at once every second iteration
+//      (x += alpha' p' + alpha p), which saves one read and one write of x
+//      per pair, and the last odd step is added when the solution is copied
+//      out;
 //   2. w = A z, fused with partial sums of w.z; A z is one sweep over the
-//      values v_ij = A_ij d_j prepared once per solve (d = D^-1);
-//   3. a one-workgroup finalize: beta, alpha and the stopping tests.
+//      values v_ij = A_ij d_j prepared once per solve (d = D^-1).
 // Every dot is reduced in a fixed order: each workgroup stores its
-// per-column partial sums with plain stores and the finalize kernel adds
-// them in a fixed order; the kernel boundary orders the stores before the
-// reads, so no device-scope fence is issued per workgroup (each such fence
-// writes back the XCD's L2). Results are bitwise deterministic run to run.
-// Columns stop independently and are frozen once stopped.
+// per-column partial sums with plain stores and the next kernel adds them in
+// a fixed order; the kernel boundary orders the stores before the reads, so
+// no device-scope fence is issued per workgroup (each such fence writes back
+// the XCD's L2). Results are bitwise deterministic run to run. Columns stop
+// independently and are frozen once stopped.
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -194,14 +199,22 @@ k_cg_init(int32_t nV, int k, int KP, const int32_t *__restrict__ order,
     store_partials(s_part, 3 * k, part);
 }
 
-// x[order[p]] = xp[p] (row-order solution back to natural order).
+// The vector update adds a column's steps to x in pairs (every second
+// iteration); a column whose last update had an even index still lacks
+// alpha p of that update: its iteration count is odd. Completes x in place
+// (xout == xp) or while copying the row-order solution back to natural order:
+// x[order[p]] = xp[p] (+ alpha_prev p[p]).
 template <typename R>
-__global__ void k_cg_unorder(int64_t n, int k, const int32_t *__restrict__ order,
-                             const R *__restrict__ xp, R *__restrict__ x) {
+__global__ void k_cg_finish_x(int64_t n, int k, const int32_t *__restrict__ order,
+                              const CgCol *__restrict__ st, const R *__restrict__ pdir,
+                              const R *xp, R *xout) {
     const int64_t e = (int64_t)blockIdx.x * T + threadIdx.x;
     if (e >= n) return;
-    const int64_t p = e / k;
-    x[(order ? (int64_t)order[p] : p) * k + (e - p * k)] = xp[e];
+    const int64_t q = e / k;
+    const int c = (int)(e - q * k);
+    R v = xp[e];
+    if (st[c].iters & 1) v += (R)st[c].alpha_prev * pdir[e];
+    xout[(order ? (int64_t)order[q] : q) * k + c] = v;
 }
 
 // Padded-row values: slot q = p * W + t holds v = A_ij d_j for the entry of
@@ -333,13 +346,13 @@ template <typename R>
 __global__ void __launch_bounds__(TR)
 k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R *__restrict__ p,
              R *__restrict__ sv, const R *__restrict__ w, const R *__restrict__ invD,
-             const CgCol *__restrict__ st_prev, CgCol *__restrict__ st_cur, int reduce,
+             const CgCol *__restrict__ st_prev, CgCol *__restrict__ st_cur, int reduce, int odd,
              const double *__restrict__ pin, int nbu, const double *__restrict__ pin2, int nbs,
              double *__restrict__ pout, CgParams prm) {
     __shared__ double s_part[2 * kMaxK];
     __shared__ double s_red[red_scratch(TR, 2)];
     __shared__ double s_tot[3 * kMaxK];
-    __shared__ double s_ab[2 * kMaxK];
+    __shared__ double s_ab[3 * kMaxK];
     __shared__ int s_on[kMaxK];
     __shared__ int s_any;
     const int t = threadIdx.x;
@@ -358,7 +371,7 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
         fw = w[e];
         fp = p[e];
         fs = sv[e];
-        fx = x[e];
+        if (odd) fx = x[e];
         fd = invD[i0];
     }
     if (t == 0) {
@@ -381,10 +394,12 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
         s_on[t] = c.active;
         s_ab[t] = c.alpha;
         s_ab[k + t] = c.beta;
+        s_ab[2 * k + t] = c.alpha_prev;
     }
     __syncthreads();
     const bool on = L.act && s_on[L.c];
     const R a = on ? (R)s_ab[L.c] : R(0), bt = on ? (R)s_ab[k + L.c] : R(0);
+    const R ap = on ? (R)s_ab[2 * k + L.c] : R(0);
     double d[2] = {0.0, 0.0};
     if (on) {
         for (int64_t tile = t0; tile < t1; ++tile) {
@@ -393,13 +408,18 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
             const int64_t e = i * k + L.c;
             const bool first = tile == t0;
             const R rv = first ? fr : r[e], wv = first ? fw : w[e], pv = first ? fp : p[e],
-                    s0 = first ? fs : sv[e], xv = first ? fx : x[e], dv = first ? fd : invD[i];
+                    s0 = first ? fs : sv[e], dv = first ? fd : invD[i];
             const R pn = dv * rv + bt * pv;
             const R sn = wv + bt * s0;
             const R rn = rv - a * sn;
             p[e] = pn;
             sv[e] = sn;
-            x[e] = xv + a * pn;
+            // x takes two steps every second iteration: x += a' p' + a p
+            // (p' the previous direction, still in p before this update)
+            if (odd) {
+                const R xv = first ? fx : x[e];
+                x[e] = xv + ap * pv + a * pn;
+            }
             r[e] = rn;
             const R zn = dv * rn;
             d[0] += (double)rn * (double)zn;
@@ -712,8 +732,8 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
             DGO_LAUNCH("cg_vupdate", st_s,
                        k_cg_vupdate<R><<<nb_v, TR, 0, st_s>>>(
                            (int32_t)nV, k, KP, x, r, p, sv, w, dvec, stt[(i + 1) & 1], stt[i & 1],
-                           i > 0 ? 1 : 0, partU[i & 1], (int)nb_v, part2, nbs, partU[(i + 1) & 1],
-                           prm));
+                           i > 0 ? 1 : 0, i & 1, partU[i & 1], (int)nb_v, part2, nbs,
+                           partU[(i + 1) & 1], prm));
             nbs = launch_sdot<R>(m, v, dvec, k, r, w, stt[i & 1], part2, st_s);
         }
     };
@@ -756,7 +776,12 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     CgCol hst[kMaxK];
     if (ell)
         DGO_LAUNCH("cg_unorder", s,
-                   k_cg_unorder<R><<<grid_for(n, T), T, 0, s>>>(n, k, m->order, x, u));
+                   k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, m->order, stt[done_iters & 1],
+                                                                 p, x, u));
+    else
+        DGO_LAUNCH("cg_unorder", s,
+                   k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, nullptr, stt[done_iters & 1],
+                                                                 p, x, x));
     DGO_LAUNCH("cg_trueres", s,
                k_cg_trueres<R><<<nb_v, TR, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta, K,
                                                   mask, k, KP, beff, u, part));

@@ -6,6 +6,7 @@ over the row, rtol = 1e-12 (FP64) or 1e-5 (FP32); in FP32 the oracle runs in
 FP64 on the same FP32-rounded positions.
 """
 import numpy as np
+import scipy.sparse as sp
 import pytest
 import torch
 
@@ -191,16 +192,18 @@ def _cfg2_system(level, k, dtype, seed=1):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_pcg_fixed_iterations_match_oracle(dtype):
-    """The same iteration count on both sides: iterates agree element by element."""
-    print(f"[pcg-fixed] {dtype}", flush=True)
+@pytest.mark.parametrize("iters", [1, 30, 31])
+def test_pcg_fixed_iterations_match_oracle(dtype, iters):
+    """The same iteration count on both sides: iterates agree element by element
+    (odd and even counts: x takes the steps in pairs)."""
+    print(f"[pcg-fixed] {dtype} {iters}", flush=True)
     m, K, M, b = _cfg2_system(5, 8, dtype)
-    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=30, fixed_iters=True)
-    assert rep["iters"] == [30] * 8
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=iters, fixed_iters=True)
+    assert rep["iters"] == [iters] * 8
     rp, col = [t.cpu().numpy() for t in m.csr()]
     uo, its, rr = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3,
                              K.double().cpu().numpy(), b.double().cpu().numpy(), rtol=0.0,
-                             max_iter=30)
+                             max_iter=iters)
     tol = 1e-10 if dtype == "f64" else 1e-4
     err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
     assert err <= tol, err
@@ -292,6 +295,27 @@ def test_pcg_strict_and_deterministic():
     # row split of the SpMV depends on k, so agreement is to rounding)
     u0, _ = dgo.pcg(m, 1.0, M, 1e-3, K, b[:, 1].contiguous(), rtol=1e-10)
     assert (u0 - u1[:, 1]).abs().max() <= 1e-9 * u1[:, 1].abs().max()
+
+
+def test_pcg_rtol_initial_matches_oracle():
+    """Stopping at a fraction of the initial residual equals the textbook
+    stop ||r|| <= rtol ||b|| with rtol = rtol_initial ||r_0|| / ||b||."""
+    print("[pcg] rtol_initial", flush=True)
+    m, K, M, b = _cfg2_system(4, 3, "f64")
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    Kh, Mh, bh = K.cpu().numpy(), M.cpu().numpy(), b.cpu().numpy()
+    u0 = 0.01 * meshgen.normal(77, bh.size).reshape(bh.shape)
+    A = sp.csr_matrix((1e-3 * Kh, col, rp)) + sp.diags(Mh)
+    r0 = np.linalg.norm(bh - A @ u0, axis=0)
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, u0=torch.from_numpy(u0).to(DEV), rtol=0.0,
+                     rtol_initial=1e-4, max_iter=2000)
+    assert rep["converged_all"]
+    for c in range(bh.shape[1]):
+        uo, its, _ = oracle.pcg(rp, col, 1.0, Mh, 1e-3, Kh, bh[:, c].copy(), u0=u0[:, c].copy(),
+                                rtol=1e-4 * r0[c] / np.linalg.norm(bh[:, c]), max_iter=2000)
+        assert abs(int(rep["iters"][c]) - int(its[0])) <= 1
+        rg = np.linalg.norm(bh[:, c] - A @ u.cpu().numpy()[:, c])
+        assert rg <= 1.05e-4 * r0[c]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
