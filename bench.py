@@ -84,8 +84,9 @@ def alg_bytes(kind, s, nV, nF, nnz, k):
         # read, y written
         return nnz * (s + 4) + 4 * (nV + 1) + s * nV + 2 * k * s * nV
     if kind == "cg_vupdate":
-        # read r w p s x, write p s x r, read D^-1
-        return 9 * k * s * nV + s * nV
+        # read r w p s, write p s r, read D^-1; x (read and written) only in
+        # every second iteration (two steps at once): 8 vectors on average
+        return 8 * k * s * nV + s * nV
     if kind == "assemble_intrinsic":
         # edge lengths and the face -> edge map read, K and M written
         return s * (nnz - nV) // 2 + 12 * nF + s * nnz + s * nV
