@@ -330,8 +330,8 @@ typedef struct {
     double inner_rtol;      /* PCG rtol of each inner solve (0: tol / 10) */
     double inner_rtol_initial; /* each inner solve also stops at this fraction
                                of its warm start's residual (0: 0.1; < 0: off) */
-    int32_t block;          /* subspace size p, k <= p <= 64 (0: min(64, nV,
-                               max(2k, k + 8))) */
+    int32_t block;          /* subspace size p, k <= p <= 64 (0: the power of
+                               two >= k + 6, at most min(64, nV), at least k) */
     int32_t max_iter;       /* outer iterations (0: 200) */
     int32_t inner_max_iter; /* PCG iteration cap per solve (0: 20000) */
     int32_t reserved;

@@ -24,6 +24,7 @@
 // consecutive eigenvalues of the unshifted operator tends to 1 as meshes grow),
 // so the inverse is applied by the same PCG as the linear solves instead.
 #include "internal.hpp"
+#include "kernels.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -471,7 +472,11 @@ extern "C" dgo_status dgo_eigs_smallest(const dgo_mesh *m, dgo_dtype dtype, cons
     if (opts) o = *opts;
     if (k < 1 || k > kEigMaxP || k > m->nV)
         return fail(DGO_ERR_INVALID_ARG, "dgo_eigs_smallest: k must be in [1, min(64, nV)]");
-    if (o.block == 0) o.block = std::min<int64_t>({(int64_t)kEigMaxP, (int64_t)m->nV, std::max(2 * k, k + 8)});
+    // default block: the power of two with at least 6 guard columns (the PCG
+    // pads its columns to a power of two, so other sizes cost the same lanes)
+    if (o.block == 0)
+        o.block = std::max<int64_t>(
+            k, std::min<int64_t>({(int64_t)kEigMaxP, (int64_t)m->nV, (int64_t)kern::pow2ceil(k + 6)}));
     if (o.block < k || o.block > kEigMaxP || o.block > m->nV)
         return fail(DGO_ERR_INVALID_ARG, "dgo_eigs_smallest: block must be in [k, min(64, nV)]");
     hipStream_t s = (hipStream_t)stream;
