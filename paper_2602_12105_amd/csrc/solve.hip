@@ -402,28 +402,42 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
     const R ap = on ? (R)s_ab[2 * k + L.c] : R(0);
     double d[2] = {0.0, 0.0};
     if (on) {
+        // software pipelined: the next tile's loads are issued before the
+        // current tile is computed and stored
+        R rv = fr, wv = fw, pv = fp, s0 = fs, xv = fx, dv = fd;
         for (int64_t tile = t0; tile < t1; ++tile) {
-            const int64_t i = tile * L.gpb + L.grp;
-            if (i >= nV) continue;
-            const int64_t e = i * k + L.c;
-            const bool first = tile == t0;
-            const R rv = first ? fr : r[e], wv = first ? fw : w[e], pv = first ? fp : p[e],
-                    s0 = first ? fs : sv[e], dv = first ? fd : invD[i];
-            const R pn = dv * rv + bt * pv;
-            const R sn = wv + bt * s0;
-            const R rn = rv - a * sn;
-            p[e] = pn;
-            sv[e] = sn;
-            // x takes two steps every second iteration: x += a' p' + a p
-            // (p' the previous direction, still in p before this update)
-            if (odd) {
-                const R xv = first ? fx : x[e];
-                x[e] = xv + ap * pv + a * pn;
+            const int64_t i = tile * L.gpb + L.grp, in = i + L.gpb;
+            R nr = 0, nw = 0, np = 0, ns = 0, nx = 0, nd = 0;
+            if (tile + 1 < t1 && in < nV) {
+                const int64_t en = in * k + L.c;
+                nr = r[en];
+                nw = w[en];
+                np = p[en];
+                ns = sv[en];
+                if (odd) nx = x[en];
+                nd = invD[in];
             }
-            r[e] = rn;
-            const R zn = dv * rn;
-            d[0] += (double)rn * (double)zn;
-            d[1] += (double)rn * (double)rn;
+            if (i < nV) {
+                const int64_t e = i * k + L.c;
+                const R pn = dv * rv + bt * pv;
+                const R sn = wv + bt * s0;
+                const R rn = rv - a * sn;
+                p[e] = pn;
+                sv[e] = sn;
+                // x takes two steps every second iteration: x += a' p' + a p
+                // (p' the previous direction, still in p before this update)
+                if (odd) x[e] = xv + ap * pv + a * pn;
+                r[e] = rn;
+                const R zn = dv * rn;
+                d[0] += (double)rn * (double)zn;
+                d[1] += (double)rn * (double)rn;
+            }
+            rv = nr;
+            wv = nw;
+            pv = np;
+            s0 = ns;
+            xv = nx;
+            dv = nd;
         }
     }
     column_partials(d, 2, k, KP, on, s_red, s_part);
