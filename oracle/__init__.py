@@ -59,6 +59,7 @@ def lib():
             "orc_face_gradient": [i32, i64, P, P, i32, P, P],
             "orc_face_divergence": [i32, i64, P, P, i32, P, P],
             "orc_mass_voronoi": [i32, i64, P, P, P],
+            "orc_slot_map": [C.c_int, i32, i64, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -382,3 +383,15 @@ def eigs_smallest(rowptr, col, K, M, k, dense_max=4000, sigma=-1e-3):
     # rounding; normalize again so the comparison metric is exact)
     V = V / np.sqrt(np.einsum("ij,i,ij->j", V, M, V))[None, :]
     return lam, canonical_sign(V)
+
+
+def slot_map(nV, elem, rowptr, col):
+    """(n_elem, nl, 2) CSR slots of each element-local pair: (a, b) in row a,
+    (b, a) in row b."""
+    elem = _i32(elem)
+    dim = _dim(elem)
+    nl = 3 if dim == 2 else 6
+    out = np.empty((elem.shape[0], nl, 2), np.int32)
+    _check(lib().orc_slot_map(dim, nV, elem.shape[0], _p(elem), _p(_i32(rowptr)), _p(_i32(col)),
+                              _p(out)), "slot_map")
+    return out

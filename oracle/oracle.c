@@ -845,3 +845,22 @@ int orc_mass_voronoi(int32_t nV, int64_t nF, const int32_t *F, const double *X, 
     }
     return ORC_OK;
 }
+
+int orc_slot_map(int dim, int32_t nV, int64_t n_elem, const int32_t *elem, const int32_t *rowptr,
+                 const int32_t *col, int32_t *slots) {
+    int st = orc_validate(dim, nV, n_elem, elem);
+    if (st) return st;
+    if (!rowptr || !col || !slots) return ORC_ERR_INVALID_ARG;
+    const int nv = dim + 1, nl = dim == 2 ? 3 : 6;
+    for (int64_t e = 0; e < n_elem; ++e)
+        for (int j = 0; j < nl; ++j) {
+            int a, b;
+            local_pair(dim, j, &a, &b);
+            const int32_t va = elem[e * nv + a], vb = elem[e * nv + b];
+            const int64_t sab = find_slot(rowptr, col, va, vb), sba = find_slot(rowptr, col, vb, va);
+            if (sab < 0 || sba < 0) return ORC_ERR_INVALID_ARG;
+            slots[(e * nl + j) * 2] = (int32_t)sab;
+            slots[(e * nl + j) * 2 + 1] = (int32_t)sba;
+        }
+    return ORC_OK;
+}

@@ -41,6 +41,14 @@ int orc_edges(int dim, int32_t nV, int64_t n_elem, const int32_t *elem,
  * ascending within a row. rowptr: nV+1, col: nV + 2 nE. */
 int orc_csr(int32_t nV, int64_t nE, const int32_t *EV, int32_t *rowptr, int32_t *col);
 
+/* Slot map (the CSR slots the scatter of Sec. 6.1 reaches through an
+ * element's local pairs): for element e and local
+ * pair slot j (the element->edge slot order of orc_edges), slots[(e*nl + j)*2]
+ * is the CSR position of (a, b) in row a and slots[(e*nl + j)*2 + 1] that of
+ * (b, a) in row b, (a, b) the pair's vertices in local order. */
+int orc_slot_map(int dim, int32_t nV, int64_t n_elem, const int32_t *elem, const int32_t *rowptr,
+                 const int32_t *col, int32_t *slots);
+
 /* Boundary: triangle meshes mark the vertices of edges with one incident
  * triangle; tetrahedral meshes mark the vertices of triangles that belong to
  * one tetrahedron. mask: nV bytes (1 = boundary). n_bfaces: number of

@@ -145,3 +145,25 @@ def test_validate(orc):
     assert orc.validate(4, np.array([[0, -1, 2]], np.int32)) == 2
     T = np.array([[0, 1, 2, 3]], np.int32)
     assert orc.validate(4, T) == 0 and orc.validate(4, np.array([[0, 1, 2, 0]], np.int32)) == 1
+
+
+def test_slot_map_brute_force(orc):
+    """Every element-local pair's two CSR slots, against a dictionary of the
+    pattern built in Python (local pair order: triangle slot j is the edge
+    opposite vertex j, tet pairs 01 02 03 12 13 23)."""
+    import meshgen
+    pairs = {2: [(1, 2), (2, 0), (0, 1)], 3: [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]}
+    for X, E in (meshgen.grid2d(5, 0.1, 1), meshgen.icosphere(1), meshgen.cube_tets(3, 0.1, 2)):
+        nV = X.shape[0]
+        EV, _, _ = orc.edges(nV, E)
+        rp, col = orc.csr(nV, EV)
+        where = {}
+        for i in range(nV):
+            for s in range(rp[i], rp[i + 1]):
+                where[(i, int(col[s]))] = s
+        sm = orc.slot_map(nV, E, rp, col)
+        dim = 2 if E.shape[1] == 3 else 3
+        for e in range(E.shape[0]):
+            for j, (a, b) in enumerate(pairs[dim]):
+                va, vb = int(E[e, a]), int(E[e, b])
+                assert sm[e, j, 0] == where[(va, vb)] and sm[e, j, 1] == where[(vb, va)]
