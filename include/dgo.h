@@ -135,6 +135,13 @@ dgo_status dgo_mesh_csr(const dgo_mesh *mesh, int32_t *d_rowptr, int32_t *d_col,
  * pointer may be NULL, not both. */
 dgo_status dgo_mesh_coo(const dgo_mesh *mesh, int32_t *d_row, int32_t *d_col, dgo_stream stream);
 
+/* Per-element CSR slot map (the slots the scatter of Sec. 6.1 reaches through
+ * an element's local pairs): d_slots (n_elem x nl x 2 int32) receives, for
+ * local pair j of element e (the slot order of dgo_mesh_edges), the CSR
+ * position of (a, b) in row a and of (b, a) in row b, (a, b) the pair's
+ * vertices in local order. */
+dgo_status dgo_mesh_slots(const dgo_mesh *mesh, int32_t *d_slots, dgo_stream stream);
+
 /* Copy out the boundary-vertex mask: d_mask (nV bytes, 1 = boundary). */
 dgo_status dgo_mesh_boundary(const dgo_mesh *mesh, uint8_t *d_mask, dgo_stream stream);
 

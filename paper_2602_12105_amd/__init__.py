@@ -110,6 +110,13 @@ class Mesh:
         check(lib().dgo_mesh_coo(self._h, _ptr(rows), _ptr(cols), _stream()), "dgo_mesh_coo")
         return rows, cols
 
+    def slots(self):
+        """(n_elem, nl, 2) CSR slots of each element-local pair: (a, b) in row
+        a and (b, a) in row b."""
+        out = torch.empty((self.n_elem, self.nl, 2), dtype=torch.int32, device=self.device)
+        check(lib().dgo_mesh_slots(self._h, _ptr(out), _stream()), "dgo_mesh_slots")
+        return out
+
     def boundary(self):
         m = torch.empty(self.nV, dtype=torch.uint8, device=self.device)
         check(lib().dgo_mesh_boundary(self._h, _ptr(m), _stream()), "dgo_mesh_boundary")

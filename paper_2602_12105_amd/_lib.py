@@ -100,6 +100,7 @@ SIGNATURES = {
     "dgo_assemble_intrinsic": (C.c_int, [P, C.c_int, i32, P, P, P, P, P, P]),
     "dgo_face_gradient": (C.c_int, [P, C.c_int, P, i32, P, P, P]),
     "dgo_mesh_coo": (C.c_int, [P, P, P, P]),
+    "dgo_mesh_slots": (C.c_int, [P, P, P]),
     "dgo_eigs_smallest": (C.c_int, [P, C.c_int, P, P, i32, P, P, P, P, P]),
     "dgo_conformal_laplacian": (C.c_int, [P, C.c_int, P, P, P, P, P]),
     "dgo_face_divergence": (C.c_int, [P, C.c_int, P, i32, P, P, P]),

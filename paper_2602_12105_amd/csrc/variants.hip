@@ -1,5 +1,5 @@
-// Operator variants on the mesh's CSR pattern: the COO form of the pattern
-// and the conformal Laplacian of the spectral conformal parameterization
+// Operator variants on the mesh's CSR pattern: the COO form of the pattern,
+// the per-element slot map, and the conformal Laplacian of the spectral conformal parameterization
 // (Sec. 7.2).
 //
 // Conformal Laplacian: for a map u = (x, y) of the mesh into the plane, the
@@ -44,6 +44,30 @@ __device__ __forceinline__ int32_t slot_of(const int32_t *__restrict__ rowptr,
         if (col[m] < j) b = m + 1; else e = m;
     }
     return b;
+}
+
+// One thread per (element, local pair j): the CSR slots of (a, b) in row a and
+// of (b, a) in row b. Local pairs: triangles, pair j is the edge opposite
+// vertex j, (j + 1, j + 2); tetrahedra 01 02 03 12 13 23.
+__global__ void k_slot_map(const int32_t *__restrict__ elem, int64_t n_elem, int dim,
+                           const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                           int32_t *__restrict__ slots) {
+    const int nv = dim + 1, nl = dim == 2 ? 3 : 6;
+    const int64_t o = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (o >= n_elem * nl) return;
+    const int64_t e = o / nl;
+    const int j = (int)(o - e * nl);
+    int a, b;
+    if (dim == 2) {
+        a = j == 2 ? 0 : j + 1;
+        b = j == 0 ? 2 : j - 1;
+    } else {
+        a = j < 3 ? 0 : (j < 5 ? 1 : 2);
+        b = j < 3 ? j + 1 : (j < 5 ? j - 1 : 3);
+    }
+    const int32_t va = elem[e * nv + a], vb = elem[e * nv + b];
+    slots[2 * o] = slot_of(rowptr, col, va, vb);
+    slots[2 * o + 1] = slot_of(rowptr, col, vb, va);
 }
 
 // One thread per (triangle, local edge): a boundary edge (one triangle) runs
@@ -144,6 +168,16 @@ extern "C" dgo_status dgo_mesh_coo(const dgo_mesh *m, int32_t *d_row, int32_t *d
     if (d_row) k_coo_rows<<<grid_for(m->nV, T), T, 0, s>>>(m->rowptr, m->nV, d_row);
     if (d_col)
         DGO_HIP(hipMemcpyAsync(d_col, m->col, sizeof(int32_t) * (size_t)m->nnz, hipMemcpyDeviceToDevice, s));
+    DGO_HIP(hipGetLastError());
+    return DGO_OK;
+}
+
+extern "C" dgo_status dgo_mesh_slots(const dgo_mesh *m, int32_t *d_slots, dgo_stream stream) {
+    clear_error();
+    if (!m || !d_slots) return fail(DGO_ERR_INVALID_ARG, "dgo_mesh_slots: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = m->n_elem * m->nl;
+    if (n) k_slot_map<<<grid_for(n, T), T, 0, s>>>(m->elem, m->n_elem, m->dim, m->rowptr, m->col, d_slots);
     DGO_HIP(hipGetLastError());
     return DGO_OK;
 }

@@ -59,6 +59,7 @@ def test_rejects_bad_arguments_without_device(dgo):
     assert b"NULL" in dgo.dgo_last_error()
     assert dgo.dgo_face_divergence(None, 1, None, 1, None, None, None) == 1
     assert dgo.dgo_mesh_coo(None, None, None, None) == 1
+    assert dgo.dgo_mesh_slots(None, None, None) == 1
     assert dgo.dgo_eigs_smallest(None, 1, None, None, 1, None, None, None, None, None) == 1
     assert dgo.dgo_conformal_laplacian(None, 1, None, None, None, None, None) == 1
     dgo.dgo_mesh_destroy(None)

@@ -97,6 +97,16 @@ def test_coo_bit_exact(name):
     np.testing.assert_array_equal(cols, col)
 
 
+@pytest.mark.parametrize("name", ["tri1", "tet1", "disjoint", "fan", "grid64", "ico7", "cube9",
+                                  "cube64"])
+def test_slot_map_bit_exact(name):
+    print(f"[slots] {name}", flush=True)
+    X, E, m = _setup(name)
+    EV, _, _ = oracle.edges(X.shape[0], E)
+    rp, col = oracle.csr(X.shape[0], EV)
+    np.testing.assert_array_equal(m.slots().cpu().numpy(), oracle.slot_map(X.shape[0], E, rp, col))
+
+
 def _dense_csr(rp, col, val, n):
     return sp.csr_matrix((val, col, rp), shape=(n, n)).toarray()
 
