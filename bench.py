@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-pool", type=int, default=256,
                     help="distinct generated payloads the arrivals are drawn from")
+    ap.add_argument("--cpu-baseline-suite", action="store_true",
+                    help="only time the FP64 oracle on every workload (single thread per "
+                         "workload, and a process pool for the batched serving and "
+                         "differentiation workloads), print one JSON line and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain elementwise copy of 256 MiB (read) into 256 MiB "
                          "(write), the reference for scaling the HBM byte counters")
@@ -133,6 +137,9 @@ def main():
                                    "supported (the sharding design is described in DESIGN.md)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.cpu_baseline_suite:
+        print(json.dumps(cpu_baseline_suite(args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -267,6 +274,21 @@ def main():
         sweeps[label] = ent
     del flush
 
+    # reference: a plain device-to-device copy of 512 MiB (read 512 MiB, write
+    # 512 MiB), beyond the last-level cache, timed with events on torch's stream
+    src = torch.ones(1 << 26, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del src, dst
+    roofline["frac_of_stream_copy"] = roofline["achieved"] / copy_gbs
+
     out = {
         "metric": "elements assembled/s + SpMV HBM GB/s (frac of peak); req/s, p50/p99 latency",
         "value": value,
@@ -289,6 +311,7 @@ def main():
         "topology_ms": topo_ms,
         "kernels": kernels,
         "kernel_sweeps": sweeps,
+        "stream_copy_gbps": copy_gbs,
         "baseline_note": PAPER_NOTE,
     }
 
@@ -371,6 +394,30 @@ def suite(args, dgo, torch, meshgen):
                             "nodal_err_vs_exact": float((u - g).abs().max())}
     out["cube64_tet"] = ent
     del m, K, M, Xd
+
+    # the same generator past the last-level cache: Kuhn cube 128^3 (2.1 M
+    # vertices, 12.3 M tets): tet assembly and SpMV, warm and cold
+    log(args, "suite: Kuhn cube 128^3")
+    X, T = meshgen.cube_tets(128, 0.15, 0)
+    m = dgo.Mesh(torch.from_numpy(T).to(dev), X.shape[0])
+    Xd = torch.from_numpy(X).to(dev, td)
+    K, M = dgo.assemble(m, Xd)
+    ent = {"nV": m.nV, "nT": m.n_elem, "nnz": m.nnz}
+    ab = alg_bytes("assemble_tet", s, m.nV, m.n_elem, m.nnz, 1)
+    abs1 = alg_bytes("spmm", s, m.nV, m.n_elem, m.nnz, 1)
+    x1 = torch.rand(m.nV, dtype=td, device=dev)
+    y1 = torch.empty_like(x1)
+    for cold in (False, True):
+        tag = "cold" if cold else "warm"
+        us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xd, out=(K, M)), "assemble_tet", reps,
+                         flush if cold else None)
+        ent["assemble_" + tag] = roof(ab, us)
+        us = kernel_time(dgo, torch, lambda: dgo.spmv(m, 0.0, M, 1.0, K, x1, out=y1), "spmm", reps,
+                         flush if cold else None)
+        ent["spmv_k1_" + tag] = roof(abs1, us)
+    ent["tets_per_s_cold"] = m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
+    out["cube128_tet"] = ent
+    del m, K, M, Xd, x1, y1, X, T
 
     # plain method on the 64 x 64 grid: 100 SpMVs with K on a uniform[-1, 1] vector
     log(args, "suite: grid 64x64")
@@ -648,6 +695,141 @@ def cpu_baseline(X, F, f, budget_s):
             "sample": f"{n} full step(s) of the same workload in {el:.1f} s, FP64, one thread "
                       f"(topology once, {topo:.2f} s, not counted); host has {os.cpu_count()} CPUs",
             "iters": [int(i) for i in its]}
+
+
+# ------------------------------------------------------ oracle on every workload
+
+_POOL_DATA = {}
+
+
+def _pool_serving(i):
+    """One serving request through the FP64 oracle: assemble, b = M f, 50 PCG
+    iterations on (M + 1e-3 K) u = b."""
+    import oracle
+    F, X, f, _ = _POOL_DATA["serving"][i]
+    X = X.astype("float64")
+    K, M, rp, col = oracle.assemble(X, F)
+    b = M[:, None] * f.astype("float64")
+    oracle.pcg(rp, col, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=50)
+    return i
+
+
+def _pool_diff(i):
+    """One mesh of the differentiation batch through the FP64 oracle: the
+    assembly, then its VJP for the loss u^T K u + sum(M)."""
+    import numpy as np
+    import oracle
+    X, F, rp, col, u = _POOL_DATA["diff"][i]
+    K, M, _, _ = oracle.assemble(X, F, rp, col)
+    rows = np.repeat(np.arange(X.shape[0]), np.diff(rp))
+    gK = u[rows] * u[col]
+    oracle.assemble_vjp_tri(X, F, rp, col, gK, np.ones(X.shape[0]))
+    return i
+
+
+def _timed_pool(fn, n, workers):
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        pool.map(fn, range(min(n, workers)))  # start the workers
+        t0 = time.perf_counter()
+        pool.map(fn, range(n), chunksize=1)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline_suite(args):
+    """The FP64 oracle (single-threaded C) on every workload, on this host.
+    Batched workloads also run in a process pool of one process per core of
+    this process's CPU share (at most 16): measured, not extrapolated."""
+    import numpy as np
+
+    import meshgen
+    import oracle
+    oracle.lib()
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    workers = max(1, min(16, cores))
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {"kind": "oracle", "dtype": "f64", "host": {"cpus_available": cores, "pool_workers": workers,
+                                                      "cpu_model": model}}
+
+    def clock(fn, reps=1):
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        return (time.perf_counter() - t0) / reps, r
+
+    # grid 64 x 64: assembly and 100 SpMVs with K
+    log(args, "cpu suite: grid 64")
+    X, F = meshgen.grid2d(64, 0.2, 0)
+    EV, _, _ = oracle.edges(X.shape[0], F)
+    rp, col = oracle.csr(X.shape[0], EV)
+    ta, (K, M, _, _) = clock(lambda: oracle.assemble(X, F, rp, col), 10)
+    x = meshgen.uniform(1, X.shape[0]) * 2 - 1
+    ts, _ = clock(lambda: [oracle.spmv(rp, col, 0.0, M, 1.0, K, x) for _ in range(100)])
+    out["grid64"] = {"assemble_ms": ta * 1e3, "spmv_x100_ms": ts * 1e3, "threads": 1}
+
+    # icosphere L7 step: assembly, b = M f, PCG to 1e-8 on 8 columns
+    log(args, "cpu suite: icosphere L7 step")
+    X, F = meshgen.icosphere(7, 1e-3, 0)
+    f = meshgen.normal(1, X.shape[0] * 8).reshape(-1, 8)
+    EV, _, _ = oracle.edges(X.shape[0], F)
+    rp, col = oracle.csr(X.shape[0], EV)
+
+    def step():
+        K, M, _, _ = oracle.assemble(X, F, rp, col)
+        b = oracle.spmv(rp, col, 1.0, M, 0.0, K, f)
+        return oracle.pcg(rp, col, 1.0, M, 1e-3, K, b, rtol=1e-8, max_iter=1000)
+    ta, _ = clock(lambda: oracle.assemble(X, F, rp, col), 3)
+    tstep, (_, its, _) = clock(step)
+    out["icosphere_L7"] = {"assemble_ms": ta * 1e3, "step_ms": tstep * 1e3,
+                           "triangles_per_s": F.shape[0] / tstep, "pcg_iters": [int(i) for i in its],
+                           "threads": 1}
+
+    # Kuhn cube 64^3: tet assembly and the Dirichlet Poisson solve to 1e-8
+    log(args, "cpu suite: Kuhn cube 64^3")
+    X, T = meshgen.cube_tets(64, 0.15, 0)
+    EV, _, _ = oracle.edges(X.shape[0], T)
+    rp, col = oracle.csr(X.shape[0], EV)
+    ta, (K, M, _, _) = clock(lambda: oracle.assemble(X, T, rp, col))
+    mask, _ = oracle.boundary(X.shape[0], T)
+    us = np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
+    b = M * (3 * np.pi ** 2 * us)
+    tp, (_, its, _) = clock(lambda: oracle.pcg(rp, col, 0.0, M, 1.0, K, b, mask=mask, g=us,
+                                                rtol=1e-8, max_iter=5000))
+    out["cube64_tet"] = {"assemble_ms": ta * 1e3, "dirichlet_pcg_ms": tp * 1e3,
+                         "pcg_iters": int(its[0]), "tets_per_s": T.shape[0] / ta, "threads": 1}
+
+    # serving requests: the first 4 * workers of the same request stream
+    log(args, "cpu suite: serving requests")
+    _POOL_DATA["serving"] = _serve_payloads(meshgen, 4 * workers, seed=0)
+    n1 = min(8, len(_POOL_DATA["serving"]))
+    t1, _ = clock(lambda: [_pool_serving(i) for i in range(n1)])
+    tp = _timed_pool(_pool_serving, len(_POOL_DATA["serving"]), workers)
+    out["serving"] = {"req_per_s_one_thread": n1 / t1, "requests_one_thread": n1,
+                      "req_per_s_pool": len(_POOL_DATA["serving"]) / tp,
+                      "requests_pool": len(_POOL_DATA["serving"]), "pool_workers": workers,
+                      "work": "FP64 assembly + b = M f + 50 PCG iterations per request"}
+
+    # differentiation batch: 256 icosphere L5 meshes, assembly + VJP each
+    log(args, "cpu suite: 256 x icosphere L5 VJP")
+    X0, F = meshgen.icosphere(5)
+    EV, _, _ = oracle.edges(X0.shape[0], F)
+    rp, col = oracle.csr(X0.shape[0], EV)
+    u = meshgen.normal(1000, X0.shape[0])
+    _POOL_DATA["diff"] = [(meshgen.icosphere(5, 1e-2, sd)[0], F, rp, col, u) for sd in range(256)]
+    t1, _ = clock(lambda: [_pool_diff(i) for i in range(16)])
+    tp = _timed_pool(_pool_diff, 256, workers)
+    out["diff_batch_ico5"] = {"meshes_per_s_one_thread": 16 / t1, "meshes_one_thread": 16,
+                              "meshes_per_s_pool": 256 / tp, "meshes_pool": 256,
+                              "pool_workers": workers,
+                              "work": "FP64 assembly + assembly VJP per mesh"}
+    return out
 
 
 if __name__ == "__main__":
