@@ -664,16 +664,14 @@ __device__ __forceinline__ VLane vlane(int k, int KP) {
 
 
 enum FinMode {
-    FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUT = 3,  // two reductions per iteration
-    FIN_SR_INIT = 4, FIN_SR_ITER = 5                         // one reduction per iteration
+    FIN_OUT = 3,                     // totals out (the true residual)
+    FIN_SR_INIT = 4, FIN_SR_ITER = 5  // PCG state: start, after an iteration
 };
 
 // Values per column in the (first) partial-sum array of a finalize mode; the
-// one-reduction modes read a second array of k values (w.z).
+// PCG modes read a second array of k values (w.z).
 __host__ __device__ inline int fin_width(int mode, int k) {
-    return (mode == FIN_INIT || mode == FIN_SR_INIT ? 3
-                                                     : (mode == FIN_BETA || mode == FIN_SR_ITER ? 2 : 1)) *
-           k;
+    return (mode == FIN_SR_INIT ? 3 : (mode == FIN_SR_ITER ? 2 : 1)) * k;
 }
 
 // Stopping tests after an iteration that produced residual norm^2 rr.
@@ -696,49 +694,13 @@ __device__ inline void cg_stop_tests(CgCol &s, double rr, const CgParams &prm) {
     }
 }
 
-// Per-column PCG state transitions from the reduced dots `tot` (layout as
-// stored by the kernel that produced them):
-//   FIN_INIT : tot = [r.z | r.r | b.b]   (start; stop at once if already small)
-//   FIN_ALPHA: tot = [p.q]               alpha = rz / pq for active columns
-//   FIN_BETA : tot = [r.z | r.r]         beta, iteration count, stopping tests
-__device__ inline void cg_state_update(int mode, CgCol &s, const double *tot, int c, int k,
-                                       const CgParams &prm) {
-    if (mode == FIN_INIT) {
-        s.rz = tot[c];
-        s.rr = tot[k + c];
-        s.bb = tot[2 * k + c];
-        s.rr0 = tot[k + c];
-        s.best = s.rr;
-        s.iters = 0;
-        s.since = 0;
-        s.stalled = 0;
-        s.pq = 0.0;
-        s.alpha = 0.0;
-        s.beta = 0.0;
-        const bool conv = !prm.fixed && sqrt(s.rr) <= prm.rtol * sqrt(s.bb);
-        s.converged = conv ? 1 : 0;
-        s.active = (!conv && prm.max_iter > 0) ? 1 : 0;
-    } else if (mode == FIN_ALPHA) {
-        const double pq = tot[c];
-        s.pq = pq;
-        s.alpha = (s.active && pq != 0.0) ? s.rz / pq : 0.0;
-    } else if (mode == FIN_BETA && s.active) {
-        const double rz_new = tot[c], rr = tot[k + c];
-        s.beta = s.rz != 0.0 ? rz_new / s.rz : 0.0;
-        s.rz = rz_new;
-        s.rr = rr;
-        s.iters += 1;
-        cg_stop_tests(s, rr, prm);
-    }
-}
-
 // One-reduction PCG (Chronopoulos and Gear's rearrangement of the same
 // iteration): every iteration needs gamma = r.z, rho = r.r and delta = w.z,
 // w = A z, z = D^-1 r, all of one residual, so they are reduced together:
 //   beta_i = gamma_i / gamma_{i-1},
 //   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1})
 // (alpha_0 = gamma_0 / delta_0, beta_0 = 0). The vector update then forms
-// p = z + beta p and s = w + beta s (s = A p), x += alpha p, r -= alpha s.
+// p = z + beta p and s = w + beta s (s = A p), r -= alpha s and the x update.
 //   FIN_SR_INIT: tot = [r.z | r.r | b.b], tot2 = [w.z]
 //   FIN_SR_ITER: tot = [r.z | r.r],       tot2 = [w.z]  (after one update)
 __device__ inline void cg_sr_update(int mode, CgCol &s, const double *tot, const double *tot2,
