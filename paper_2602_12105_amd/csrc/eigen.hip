@@ -102,18 +102,33 @@ k_eig_gram(int64_t n, int p, int64_t chunk, const R *__restrict__ Y, const R *__
     }
 }
 
-// Sum the partials of each pair over the blocks in block order.
-__global__ void k_eig_gram_final(int nblk, int pp, const double *__restrict__ partG,
-                                 const double *__restrict__ partH, double *__restrict__ GH) {
-    const int q = blockIdx.x * ET + threadIdx.x;
-    if (q >= pp) return;
+// Sum the partials of each pair over the blocks: one workgroup per pair,
+// thread t adds blocks t, t + ET, ... in order, then a fixed-shape tree in
+// LDS; the same order on every run.
+__global__ void __launch_bounds__(ET)
+k_eig_gram_final(int nblk, int pp, const double *__restrict__ partG,
+                 const double *__restrict__ partH, double *__restrict__ GH) {
+    __shared__ double sg[ET], sh[ET];
+    const int q = blockIdx.x, t = threadIdx.x;
     double g = 0.0, h = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = t; b < nblk; b += ET) {
         g += partG[(int64_t)b * pp + q];
         h += partH[(int64_t)b * pp + q];
     }
-    GH[q] = g;
-    GH[pp + q] = h;
+    sg[t] = g;
+    sh[t] = h;
+    __syncthreads();
+    for (int w = ET / 2; w > 0; w /= 2) {
+        if (t < w) {
+            sg[t] += sg[t + w];
+            sh[t] += sh[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        GH[q] = sg[0];
+        GH[pp + q] = sh[0];
+    }
 }
 
 // U = Y C, KU = KY C (C: p x p, FP64, staged in LDS)
@@ -184,26 +199,47 @@ k_eig_resid(int64_t n, int p, int64_t chunk, const R *__restrict__ U, const R *_
     }
 }
 
-// Reduce the per-block column results in block order: out[j] = residual sum,
-// out[p + j] = signed value of the largest-magnitude entry (first on ties).
+// Reduce the per-block column results, one workgroup per column (the same
+// fixed order as the Gram reduction): out[j] = residual sum, out[p + j] =
+// signed value of the largest-magnitude entry (the first on ties).
 template <typename R>
-__global__ void k_eig_resid_final(int nblk, int p, const double *__restrict__ part,
-                                  const R *__restrict__ U, double *__restrict__ out) {
-    const int j = threadIdx.x;
-    if (j >= p) return;
+__global__ void __launch_bounds__(ET)
+k_eig_resid_final(int nblk, int p, const double *__restrict__ part, const R *__restrict__ U,
+                  double *__restrict__ out) {
+    __shared__ double ss[ET], sm[ET];
+    __shared__ int64_t si[ET];
+    const int j = blockIdx.x, t = threadIdx.x;
     double s = 0.0, mx = -1.0;
     int64_t ix = -1;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = t; b < nblk; b += ET) {
         const double *pb = part + (int64_t)b * 3 * p;
         s += pb[j];
         const int64_t bi = (int64_t)pb[2 * p + j];
-        if (pb[p + j] > mx || (pb[p + j] == mx && bi >= 0 && bi < ix)) {
+        if (pb[p + j] > mx) {  // blocks visited in increasing row order
             mx = pb[p + j];
             ix = bi;
         }
     }
-    out[j] = s;
-    out[p + j] = ix >= 0 ? (double)U[ix * p + j] : 0.0;
+    ss[t] = s;
+    sm[t] = mx;
+    si[t] = ix;
+    __syncthreads();
+    for (int w = ET / 2; w > 0; w /= 2) {
+        if (t < w) {
+            ss[t] += ss[t + w];
+            const double m2 = sm[t + w];
+            const int64_t i2 = si[t + w];
+            if (m2 > sm[t] || (m2 == sm[t] && i2 >= 0 && (si[t] < 0 || i2 < si[t]))) {
+                sm[t] = m2;
+                si[t] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[j] = ss[0];
+        out[p + j] = si[0] >= 0 ? (double)U[si[0] * p + j] : 0.0;
+    }
 }
 
 // B = M U (the right-hand sides) and X = U diag(s) (the warm start)
@@ -294,7 +330,7 @@ dgo_status run_eigs(const dgo_mesh *m, dgo_dtype dt, const R *M, const R *K, int
         }
         DGO_TRY(dgo_spmv(m, dt, 1, 0.0, M, 1.0, K, p, Y, KY, (dgo_stream)s));
         k_eig_gram<R><<<nblk, ET, 0, s>>>(n, p, chunk, Y, KY, M, partG, partH);
-        k_eig_gram_final<<<grid_for(pp, ET), ET, 0, s>>>(nblk, pp, partG, partH, GH);
+        k_eig_gram_final<<<pp, ET, 0, s>>>(nblk, pp, partG, partH, GH);
         DGO_HIP(hipGetLastError());
         DGO_HIP(hipMemcpyAsync(hGH.data(), GH, sizeof(double) * 2 * pp, hipMemcpyDeviceToHost, s));
         DGO_HIP(hipStreamSynchronize(s));
@@ -306,7 +342,7 @@ dgo_status run_eigs(const dgo_mesh *m, dgo_dtype dt, const R *M, const R *K, int
         DGO_LAUNCH("eig_rayleigh_ritz", s, {
             k_eig_combine<R><<<grid_for(n * p, ET), ET, 0, s>>>(n, p, Y, KY, Cd, U, KU);
             k_eig_resid<R><<<nblk, ET, 0, s>>>(n, p, chunk, U, KU, M, vec, partR);
-            k_eig_resid_final<R><<<1, kEigMaxP, 0, s>>>(nblk, p, partR, U, rout);
+            k_eig_resid_final<R><<<p, ET, 0, s>>>(nblk, p, partR, U, rout);
         });
         DGO_HIP(hipGetLastError());
         DGO_HIP(hipMemcpyAsync(hr.data(), rout, sizeof(double) * 2 * p, hipMemcpyDeviceToHost, s));

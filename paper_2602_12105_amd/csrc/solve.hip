@@ -702,7 +702,11 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     prm.stall = o.stall_iters;
     prm.k = k;
 
+    // the vector update runs on at most 256 workgroups (each of them adds
+    // every partial sum of the previous iteration first); the true-residual
+    // SpMV after the loop uses the full grid
     const unsigned nb_v = nblocks_for(ntiles(nV, TR / KP), 256);
+    const unsigned nb_t = nblocks_for(ntiles(nV, TR / KP), kMaxRedBlocks);
     const R ra = (R)alpha, rb = (R)beta;
 
     DGO_LAUNCH("cg_invdiag", s,
@@ -797,9 +801,9 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
                    k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, nullptr, stt[done_iters & 1],
                                                                  p, x, x));
     DGO_LAUNCH("cg_trueres", s,
-               k_cg_trueres<R><<<nb_v, TR, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta, K,
+               k_cg_trueres<R><<<nb_t, TR, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta, K,
                                                   mask, k, KP, beff, u, part));
-    launch_fin<FIN_OUT>(part, (int)nb_v, nullptr, 0, k, nullptr, nullptr, prm, tr, s);
+    launch_fin<FIN_OUT>(part, (int)nb_t, nullptr, 0, k, nullptr, nullptr, prm, tr, s);
     DGO_HIP(hipGetLastError());
     double htr[kMaxK];
     DGO_HIP(hipMemcpyAsync(hst, stt[done_iters & 1], sizeof(CgCol) * k, hipMemcpyDeviceToHost, s));
