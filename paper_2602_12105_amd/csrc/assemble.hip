@@ -317,10 +317,12 @@ dgo_status launch_assemble(const dgo_mesh *m, int32_t batch, const void *X,
     const R cm = o ? (R)o->clamp_min : R(0);
     const int mk = o ? o->mass : 0;
     if (m->dim == 2)
-        DGO_LAUNCH("assemble_tri", s,
-                   k_assemble<R, 2><<<grid, kAssembleThreads, lds, s>>>(
+    {
+        auto kfn = k_assemble<R, 2>;
+        DGO_LAUNCH_EXT("assemble_tri", s, kfn, grid, dim3(kAssembleThreads), (uint32_t)lds,
                        view_of(m), m->nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg,
-                       mk));
+                       mk);
+    }
     else
         DGO_LAUNCH("assemble_tet", s,
                    k_assemble<R, 3><<<grid, kAssembleThreads, lds, s>>>(

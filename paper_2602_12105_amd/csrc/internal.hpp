@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <cstdio>
@@ -52,6 +53,27 @@ struct TraceScope {
     do {                                            \
         ::dgo::TraceScope trace_scope_(name, stream); \
         __VA_ARGS__;                                \
+    } while (0)
+
+// Timing carried by the dispatch itself: the start and stop events of
+// hipExtLaunchKernel mark the kernel's own start and end (what a profiler's
+// kernel trace measures), without event packets between back-to-back
+// kernels. Used for the kernels whose rates are reported.
+struct TracePair {
+    const char *name;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    explicit TracePair(const char *n);
+    ~TracePair();
+};
+
+#define DGO_LAUNCH_EXT(name, stream, kernel, grid, block, shmem, ...)                          \
+    do {                                                                                       \
+        ::dgo::TracePair trace_pair_(name);                                                    \
+        if (trace_pair_.e0)                                                                    \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, trace_pair_.e0,          \
+                                  trace_pair_.e1, 0, __VA_ARGS__);                             \
+        else                                                                                   \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);               \
     } while (0)
 
 // ------------------------------------------------------------ allocation

@@ -547,9 +547,9 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
                     int k, const R *x, R *y, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
     dim3 grid(nblocks_for(ntiles(m->nV, T / G)), (unsigned)batch);
-    DGO_LAUNCH("spmm", s,
-               k_spmm<R, KP><<<grid, T, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV, m->nnz, alpha,
-                                                M, beta, K, k, x, y));
+    auto kfn = k_spmm<R, KP>;
+    DGO_LAUNCH_EXT("spmm", s, kfn, grid, dim3(T), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
+                   alpha, M, beta, K, k, x, y);
 }
 
 template <typename R>
@@ -612,14 +612,17 @@ int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R 
                    const CgCol *st, double *part, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
     const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), kMaxRedBlocks);
-    if (m->ell_w)
-        DGO_LAUNCH("cg_sdot", s,
-                   k_cg_sdot<R, KP, true><<<nb, TR, 0, s>>>(nullptr, nullptr, m->ell_w, m->ell_col,
-                                                            m->nV, v, dvec, k, r, w, st, part));
-    else
-        DGO_LAUNCH("cg_sdot", s,
-                   k_cg_sdot<R, KP, false><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, 0, m->col, m->nV, v,
-                                                             dvec, k, r, w, st, part));
+    if (m->ell_w) {
+        auto kfn = k_cg_sdot<R, KP, true>;
+        DGO_LAUNCH_EXT("cg_sdot", s, kfn, dim3(nb), dim3(TR), 0u, (const int2 *)nullptr,
+                       (const uint8_t *)nullptr, m->ell_w, (const int32_t *)m->ell_col, m->nV, v, dvec,
+                       k, r, w, st, part);
+    } else {
+        auto kfn = k_cg_sdot<R, KP, false>;
+        DGO_LAUNCH_EXT("cg_sdot", s, kfn, dim3(nb), dim3(TR), 0u, (const int2 *)m->rdesc,
+                       (const uint8_t *)m->rlen, 0, (const int32_t *)m->col, m->nV, v, dvec, k, r, w,
+                       st, part);
+    }
     return (int)nb;
 }
 
@@ -747,11 +750,10 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     auto iterate = [&](hipStream_t st_s, int32_t i0, int32_t count) {
         for (int32_t it = 0; it < count; ++it) {
             const int32_t i = i0 + it;
-            DGO_LAUNCH("cg_vupdate", st_s,
-                       k_cg_vupdate<R><<<nb_v, TR, 0, st_s>>>(
+            DGO_LAUNCH_EXT("cg_vupdate", st_s, k_cg_vupdate<R>, dim3(nb_v), dim3(TR), 0u,
                            (int32_t)nV, k, KP, x, r, p, sv, w, dvec, stt[(i + 1) & 1], stt[i & 1],
                            i > 0 ? 1 : 0, i & 1, partU[i & 1], (int)nb_v, part2, nbs,
-                           partU[(i + 1) & 1], prm));
+                           partU[(i + 1) & 1], prm);
             nbs = launch_sdot<R>(m, v, dvec, k, r, w, stt[i & 1], part2, st_s);
         }
     };

@@ -87,6 +87,26 @@ TraceScope::~TraceScope() {
     if (g_pending.size() > 4096) resolve_locked();
 }
 
+TracePair::TracePair(const char *n) : name(n) {
+    if (!g_on.load(std::memory_order_relaxed)) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_filter.empty() && !strstr(n, g_filter.c_str())) return;
+    e0 = take_event();
+    e1 = take_event();
+    if (!e0 || !e1) {
+        if (e0) g_pool.push_back(e0);
+        if (e1) g_pool.push_back(e1);
+        e0 = e1 = nullptr;
+    }
+}
+
+TracePair::~TracePair() {
+    if (!e0) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_pending.push_back({name, e0, e1});
+    if (g_pending.size() > 4096) resolve_locked();
+}
+
 bool trace_active() { return g_on.load(std::memory_order_relaxed); }
 
 }  // namespace dgo
