@@ -133,14 +133,13 @@ extern "C" dgo_status dgo_face_gradient(const dgo_mesh *m, dgo_dtype dtype, cons
     hipStream_t s = (hipStream_t)stream;
     const int64_t nF = m->n_elem;
     if (nF == 0) return DGO_OK;
+    const dim3 grid(grid_for(nF, kFaceThreads)), block(kFaceThreads);
     if (dtype == DGO_F64)
-        DGO_LAUNCH("face_gradient", s,
-                   k_face_gradient<double><<<grid_for(nF, kFaceThreads), kFaceThreads, 0, s>>>(
-                       m->elem, (const double *)d_X, nF, k, (const double *)d_u, (double *)d_g));
+        DGO_LAUNCH_EXT("face_gradient", s, k_face_gradient<double>, grid, block, 0u, m->elem,
+                       (const double *)d_X, nF, k, (const double *)d_u, (double *)d_g);
     else
-        DGO_LAUNCH("face_gradient", s,
-                   k_face_gradient<float><<<grid_for(nF, kFaceThreads), kFaceThreads, 0, s>>>(
-                       m->elem, (const float *)d_X, nF, k, (const float *)d_u, (float *)d_g));
+        DGO_LAUNCH_EXT("face_gradient", s, k_face_gradient<float>, grid, block, 0u, m->elem,
+                       (const float *)d_X, nF, k, (const float *)d_u, (float *)d_g);
     DGO_HIP(hipGetLastError());
     return DGO_OK;
 }
