@@ -30,7 +30,43 @@ std::vector<hipEvent_t> g_pool;
 std::vector<Rec> g_pending;
 std::map<std::string, Agg> g_agg;
 
+void add_locked(const Rec &r, float ms) {
+    Agg &a = g_agg[r.name];
+    a.count += 1;
+    a.total += ms;
+    a.mn = std::min(a.mn, (double)ms);
+    a.mx = std::max(a.mx, (double)ms);
+}
+
+// Resolve the oldest pending records whose stop event has already completed
+// (non-blocking), so the events come back to the pool while the device is
+// still working and no event is created inside a timed loop once the pool
+// has reached the depth of work in flight.
+void recycle_completed_locked() {
+    size_t n = 0;
+    while (n < g_pending.size()) {
+        const hipError_t q = hipEventQuery(g_pending[n].e1);
+        if (q != hipSuccess) {
+            (void)hipGetLastError();
+            break;
+        }
+        ++n;
+    }
+    for (size_t i = 0; i < n; ++i) {
+        Rec &r = g_pending[i];
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess)
+            add_locked(r, ms);
+        else
+            (void)hipGetLastError();
+        g_pool.push_back(r.e0);
+        g_pool.push_back(r.e1);
+    }
+    g_pending.erase(g_pending.begin(), g_pending.begin() + (std::ptrdiff_t)n);
+}
+
 hipEvent_t take_event() {
+    if (g_pool.empty()) recycle_completed_locked();
     if (!g_pool.empty()) {
         hipEvent_t e = g_pool.back();
         g_pool.pop_back();
@@ -48,11 +84,7 @@ void resolve_locked() {
     for (Rec &r : g_pending) {
         float ms = 0.f;
         if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
-            Agg &a = g_agg[r.name];
-            a.count += 1;
-            a.total += ms;
-            a.mn = std::min(a.mn, (double)ms);
-            a.mx = std::max(a.mx, (double)ms);
+            add_locked(r, ms);
         } else {
             (void)hipGetLastError();
         }
