@@ -342,6 +342,9 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
 // the same fixed order, so all agree bitwise, and workgroup 0 stores S_i to
 // st_cur. pin, pout and st_prev, st_cur are distinct buffers (alternating
 // with the iteration's parity), so no workgroup reads what another writes.
+// tiles of the vector update whose loads are issued before its reduction
+constexpr int kVuPre = 4;
+
 template <typename R>
 __global__ void __launch_bounds__(TR)
 k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R *__restrict__ p,
@@ -357,22 +360,26 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
     __shared__ int s_any;
     const int t = threadIdx.x;
     const CgCol *sin = reduce ? st_prev : st_cur;
-    // The first tile's vectors do not depend on alpha and beta: their loads
-    // are issued before the reduction below, which they overlap.
+    // The vectors of the block's first tiles do not depend on alpha and beta:
+    // their loads are all issued before the reduction below, which they
+    // overlap (one workgroup per CU, so the registers are there).
     const VLane L = vlane(k, KP);
     int64_t t0, t1;
     tile_range(((int64_t)nV + L.gpb - 1) / L.gpb, t0, t1);
-    const int64_t i0 = t0 * L.gpb + L.grp;
-    const bool pre = L.act && t0 < t1 && i0 < nV;
-    R fr = 0, fw = 0, fp = 0, fs = 0, fx = 0, fd = 0;
-    if (pre) {
-        const int64_t e = i0 * k + L.c;
-        fr = r[e];
-        fw = w[e];
-        fp = p[e];
-        fs = sv[e];
-        if (odd) fx = x[e];
-        fd = invD[i0];
+    R fr[kVuPre], fw[kVuPre], fp[kVuPre], fs[kVuPre], fx[kVuPre], fd[kVuPre];
+#pragma unroll
+    for (int u = 0; u < kVuPre; ++u) {
+        const int64_t i = (t0 + u) * L.gpb + L.grp;
+        fr[u] = fw[u] = fp[u] = fs[u] = fx[u] = fd[u] = R(0);
+        if (L.act && t0 + u < t1 && i < nV) {
+            const int64_t e = i * k + L.c;
+            fr[u] = r[e];
+            fw[u] = w[e];
+            fp[u] = p[e];
+            fs[u] = sv[e];
+            if (odd) fx[u] = x[e];
+            fd[u] = invD[i];
+        }
     }
     if (t == 0) {
         int any = 0;
@@ -402,10 +409,43 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
     const R ap = on ? (R)s_ab[2 * k + L.c] : R(0);
     double d[2] = {0.0, 0.0};
     if (on) {
-        // software pipelined: the next tile's loads are issued before the
-        // current tile is computed and stored
-        R rv = fr, wv = fw, pv = fp, s0 = fs, xv = fx, dv = fd;
-        for (int64_t tile = t0; tile < t1; ++tile) {
+        auto update = [&](int64_t i, R rv, R wv, R pv, R s0, R xv, R dv) {
+            const int64_t e = i * k + L.c;
+            const R pn = dv * rv + bt * pv;
+            const R sn = wv + bt * s0;
+            const R rn = rv - a * sn;
+            p[e] = pn;
+            sv[e] = sn;
+            // x takes two steps every second iteration: x += a' p' + a p
+            // (p' the previous direction, still in p before this update)
+            if (odd) x[e] = xv + ap * pv + a * pn;
+            r[e] = rn;
+            const R zn = dv * rn;
+            d[0] += (double)rn * (double)zn;
+            d[1] += (double)rn * (double)rn;
+        };
+#pragma unroll
+        for (int u = 0; u < kVuPre; ++u) {
+            const int64_t i = (t0 + u) * L.gpb + L.grp;
+            if (t0 + u < t1 && i < nV) update(i, fr[u], fw[u], fp[u], fs[u], fx[u], fd[u]);
+        }
+        // the remaining tiles, software pipelined: the next tile's loads are
+        // issued before the current tile is computed and stored
+        const int64_t tb = t0 + kVuPre;
+        R rv = 0, wv = 0, pv = 0, s0 = 0, xv = 0, dv = 0;
+        if (tb < t1) {
+            const int64_t i = tb * L.gpb + L.grp;
+            if (i < nV) {
+                const int64_t e = i * k + L.c;
+                rv = r[e];
+                wv = w[e];
+                pv = p[e];
+                s0 = sv[e];
+                if (odd) xv = x[e];
+                dv = invD[i];
+            }
+        }
+        for (int64_t tile = tb; tile < t1; ++tile) {
             const int64_t i = tile * L.gpb + L.grp, in = i + L.gpb;
             R nr = 0, nw = 0, np = 0, ns = 0, nx = 0, nd = 0;
             if (tile + 1 < t1 && in < nV) {
@@ -417,21 +457,7 @@ k_cg_vupdate(int32_t nV, int k, int KP, R *__restrict__ x, R *__restrict__ r, R 
                 if (odd) nx = x[en];
                 nd = invD[in];
             }
-            if (i < nV) {
-                const int64_t e = i * k + L.c;
-                const R pn = dv * rv + bt * pv;
-                const R sn = wv + bt * s0;
-                const R rn = rv - a * sn;
-                p[e] = pn;
-                sv[e] = sn;
-                // x takes two steps every second iteration: x += a' p' + a p
-                // (p' the previous direction, still in p before this update)
-                if (odd) x[e] = xv + ap * pv + a * pn;
-                r[e] = rn;
-                const R zn = dv * rn;
-                d[0] += (double)rn * (double)zn;
-                d[1] += (double)rn * (double)rn;
-            }
+            if (i < nV) update(i, rv, wv, pv, s0, xv, dv);
             rv = nr;
             wv = nw;
             pv = np;
