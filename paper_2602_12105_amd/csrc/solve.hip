@@ -343,7 +343,7 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
 // st_cur. pin, pout and st_prev, st_cur are distinct buffers (alternating
 // with the iteration's parity), so no workgroup reads what another writes.
 // tiles of the vector update whose loads are issued before its reduction
-constexpr int kVuPre = 4;
+constexpr int kVuPre = 5;
 
 template <typename R>
 __global__ void __launch_bounds__(TR)
