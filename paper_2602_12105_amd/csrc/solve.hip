@@ -333,15 +333,16 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
 }
 
 // The vector work of iteration i on the active columns: p = z + beta p,
-// s = w + beta s, x += alpha p, r -= alpha s (z = D^-1 r), fused with partial
-// sums of r.z and r.r of the new residual (stored to pout). The iteration's
-// state S_i (alpha, beta, stopping) is either read from st_cur (first
-// iteration of a chunk, computed by a finalize kernel) or, with reduce,
-// computed here from S_{i-1} (st_prev) and the partial sums of the previous
-// update (pin) and of w.z (pin2): every workgroup adds the same partials in
-// the same fixed order, so all agree bitwise, and workgroup 0 stores S_i to
-// st_cur. pin, pout and st_prev, st_cur are distinct buffers (alternating
-// with the iteration's parity), so no workgroup reads what another writes.
+// s = w + beta s, r -= alpha s (z = D^-1 r) and, in odd iterations, the two
+// steps x += alpha' p' + alpha p, fused with partial sums of r.z and r.r of
+// the new residual (stored to pout). The iteration's state S_i (alpha, beta,
+// stopping) is either read from st_cur (iteration 0, whose state the start
+// finalize computed) or, with reduce, computed here from S_{i-1} (st_prev)
+// and the partial sums of the previous update (pin) and of w.z (pin2): every
+// workgroup adds the same partials in the same fixed order, so all agree
+// bitwise, and workgroup 0 stores S_i to st_cur. pin, pout and st_prev,
+// st_cur are distinct buffers (alternating with the iteration's parity), so
+// no workgroup reads what another writes.
 // tiles of the vector update whose loads are issued before its reduction
 constexpr int kVuPre = 5;
 
