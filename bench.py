@@ -356,6 +356,32 @@ def roof(ab, us):
     return {"us": us, "alg_bytes": ab, "gbps": gbs, "frac": gbs / HBM_PEAK_GBS}
 
 
+def _cube_sweep(args, dgo, torch, meshgen, dev, td, s, reps, flush, nc, out):
+    """Tet assembly and SpMV (k = 1) on the Kuhn cube nc^3, warm and cold."""
+    log(args, f"suite: Kuhn cube {nc}^3")
+    X, T = meshgen.cube_tets(nc, 0.15, 0)
+    m = dgo.Mesh(torch.from_numpy(T).to(dev), X.shape[0])
+    Xd = torch.from_numpy(X).to(dev, td)
+    K, M = dgo.assemble(m, Xd)
+    ent = {"nV": m.nV, "nT": m.n_elem, "nnz": m.nnz}
+    ab = alg_bytes("assemble_tet", s, m.nV, m.n_elem, m.nnz, 1)
+    abs1 = alg_bytes("spmm", s, m.nV, m.n_elem, m.nnz, 1)
+    x1 = torch.rand(m.nV, dtype=td, device=dev)
+    y1 = torch.empty_like(x1)
+    for cold in (False, True):
+        tag = "cold" if cold else "warm"
+        us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xd, out=(K, M)), "assemble_tet", reps,
+                         flush if cold else None)
+        ent["assemble_" + tag] = roof(ab, us)
+        us = kernel_time(dgo, torch, lambda: dgo.spmv(m, 0.0, M, 1.0, K, x1, out=y1), "spmm", reps,
+                         flush if cold else None)
+        ent["spmv_k1_" + tag] = roof(abs1, us)
+    ent["tets_per_s_cold"] = m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
+    out[f"cube{nc}_tet"] = ent
+    del m, K, M, Xd, x1, y1
+    torch.cuda.empty_cache()
+
+
 def suite(args, dgo, torch, meshgen):
     """The other workloads, each timed per kernel (warm and cache-flushed)."""
     dev = torch.device("cuda:0")
@@ -400,29 +426,11 @@ def suite(args, dgo, torch, meshgen):
     out["cube64_tet"] = ent
     del m, K, M, Xd
 
-    # the same generator past the last-level cache: Kuhn cube 128^3 (2.1 M
-    # vertices, 12.3 M tets): tet assembly and SpMV, warm and cold
-    log(args, "suite: Kuhn cube 128^3")
-    X, T = meshgen.cube_tets(128, 0.15, 0)
-    m = dgo.Mesh(torch.from_numpy(T).to(dev), X.shape[0])
-    Xd = torch.from_numpy(X).to(dev, td)
-    K, M = dgo.assemble(m, Xd)
-    ent = {"nV": m.nV, "nT": m.n_elem, "nnz": m.nnz}
-    ab = alg_bytes("assemble_tet", s, m.nV, m.n_elem, m.nnz, 1)
-    abs1 = alg_bytes("spmm", s, m.nV, m.n_elem, m.nnz, 1)
-    x1 = torch.rand(m.nV, dtype=td, device=dev)
-    y1 = torch.empty_like(x1)
-    for cold in (False, True):
-        tag = "cold" if cold else "warm"
-        us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xd, out=(K, M)), "assemble_tet", reps,
-                         flush if cold else None)
-        ent["assemble_" + tag] = roof(ab, us)
-        us = kernel_time(dgo, torch, lambda: dgo.spmv(m, 0.0, M, 1.0, K, x1, out=y1), "spmm", reps,
-                         flush if cold else None)
-        ent["spmv_k1_" + tag] = roof(abs1, us)
-    ent["tets_per_s_cold"] = m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
-    out["cube128_tet"] = ent
-    del m, K, M, Xd, x1, y1, X, T
+    # the same generator past the last-level cache: Kuhn cubes 128^3 (2.1 M
+    # vertices, 12.3 M tets) and 160^3 (4.1 M vertices, 24.1 M tets): tet
+    # assembly and SpMV, warm and cold
+    for nc in (128, 160):
+        _cube_sweep(args, dgo, torch, meshgen, dev, td, s, reps, flush, nc, out)
 
     # plain method on the 64 x 64 grid: 100 SpMVs with K on a uniform[-1, 1] vector
     log(args, "suite: grid 64x64")
