@@ -38,6 +38,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 
@@ -784,38 +785,74 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
             nbs = launch_sdot<R>(m, v, dvec, k, r, w, stt[i & 1], part2, st_s);
         }
     };
-    // Progress polling without idling the device: chunk n + 1 is queued
-    // before the host waits for the state copied after chunk n, so the
-    // device never waits for the host's check. Once every column has stopped,
-    // the queued chunk finds no active column and does next to nothing.
+    // Progress polling without idling the device: up to two chunks are in
+    // flight, so the next one is queued before the host waits for the state
+    // copied after the previous one. Once every column has stopped, queued
+    // launches find no active column and do next to nothing; to queue few of
+    // them, the host plans how far to queue from each active column's
+    // residual rate (two successive polled states give its geometric rate per
+    // iteration, hence the iterations it still needs). The plan only sets how
+    // many launches are queued: every column stops on the device's own test,
+    // and a column that runs past the plan gets further chunks.
     dgo_mesh *mm = const_cast<dgo_mesh *>(m);
     if (!mm->poll_host) {
         DGO_HIP(hipHostMalloc(&mm->poll_host, 2 * sizeof(CgCol) * kMaxK, hipHostMallocDefault));
         for (auto &e : mm->poll_ev) DGO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     CgCol *hpoll = (CgCol *)mm->poll_host;
-    int32_t done_iters = 0;
-    int prev = -1;  // slot of the last queued chunk whose state is unchecked
-    for (;;) {
-        const int32_t chunk = std::min(every, o.max_iter - done_iters);
-        int cur = -1;
-        if (chunk > 0) {
-            cur = prev == 0 ? 1 : 0;
-            iterate(s, done_iters, chunk);
-            done_iters += chunk;
-            DGO_HIP(hipMemcpyAsync(hpoll + cur * kMaxK, stt[(done_iters - 1) & 1], sizeof(CgCol) * k,
-                                   hipMemcpyDeviceToHost, s));
-            DGO_HIP(hipEventRecord(mm->poll_ev[cur], s));
-            DGO_HIP(hipGetLastError());
+    const int32_t cap = std::max<int32_t>(o.max_iter, 0);
+    int32_t done_iters = 0, plan_end = cap;
+    int flight[2], nflight = 0, next_slot = 0;
+    double last_rr[kMaxK];
+    int32_t last_it[kMaxK];
+    for (int c = 0; c < k; ++c) {
+        last_rr[c] = 0.0;
+        last_it[c] = -1;
+    }
+    auto queue_chunk = [&](int32_t len) -> dgo_status {
+        const int slot = next_slot;
+        next_slot ^= 1;
+        iterate(s, done_iters, len);
+        done_iters += len;
+        DGO_HIP(hipMemcpyAsync(hpoll + slot * kMaxK, stt[(done_iters - 1) & 1], sizeof(CgCol) * k,
+                               hipMemcpyDeviceToHost, s));
+        DGO_HIP(hipEventRecord(mm->poll_ev[slot], s));
+        DGO_HIP(hipGetLastError());
+        flight[nflight++] = slot;
+        return DGO_OK;
+    };
+    if (cap > 0) DGO_TRY(queue_chunk(std::min(every, cap)));
+    while (nflight > 0) {
+        if (nflight < 2 && done_iters < plan_end) DGO_TRY(queue_chunk(std::min(every, plan_end - done_iters)));
+        const int slot = flight[0];
+        flight[0] = flight[1];
+        --nflight;
+        DGO_HIP(hipEventSynchronize(mm->poll_ev[slot]));
+        const CgCol *sc = hpoll + slot * kMaxK;
+        bool any = false, known = !o.fixed_iters;
+        int64_t need_end = 0;
+        for (int c = 0; c < k; ++c) {
+            const CgCol &q = sc[c];
+            if (!q.active) continue;
+            any = true;
+            double target = o.rtol * o.rtol * q.bb;
+            if (o.rtol_initial > 0.0) target = std::max(target, o.rtol_initial * o.rtol_initial * q.rr0);
+            if (last_it[c] >= 0 && q.iters > last_it[c] && q.rr > 0.0 && q.rr < last_rr[c] && target > 0.0) {
+                // log of the residual norm^2 ratio per iteration (< 0)
+                const double rate = std::log(q.rr / last_rr[c]) / (double)(q.iters - last_it[c]);
+                const double more = q.rr > target ? std::ceil(std::log(target / q.rr) / rate) : 0.0;
+                // the state of iteration i reaches the host after chunk end i + 1
+                need_end = std::max<int64_t>(need_end, q.iters + (int64_t)std::min(more, 1e9) + 2);
+            } else {
+                known = false;
+            }
+            last_rr[c] = q.rr;
+            last_it[c] = q.iters;
         }
-        if (prev >= 0) {
-            DGO_HIP(hipEventSynchronize(mm->poll_ev[prev]));
-            bool any = false;
-            for (int c = 0; c < k; ++c) any = any || hpoll[prev * kMaxK + c].active;
-            if (!any) break;
-        }
-        if (cur < 0) break;
-        prev = cur;
+        if (!any) break;
+        plan_end = known ? (int32_t)std::min<int64_t>(cap, need_end) : cap;
+        if (nflight == 0 && done_iters >= plan_end)  // a column outran the plan
+            plan_end = std::min(cap, done_iters + 2);
     }
     if (done_iters > 0)
         launch_fin<FIN_SR_ITER>(partU[done_iters & 1], (int)nb_v, part2, nbs, k,
