@@ -371,13 +371,15 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
 }
 
 // Contiguous chunk of tiles for this workgroup; each XCD's workgroups cover
-// one contiguous range of tiles, so neighbouring rows share an L2.
+// one contiguous range of tiles, so neighbouring rows share an L2. The
+// chunks differ in length by at most one tile, so every XCD gets an equal
+// share (chunks of ceil(ntiles / nb) would leave the last workgroups, and
+// with them whole XCDs, without work).
 __device__ __forceinline__ void tile_range(int64_t ntiles, int64_t &t0, int64_t &t1) {
     const uint32_t nb = gridDim.x;
     const uint32_t lb = xcd_tile(blockIdx.x, nb);
-    const int64_t per = (ntiles + nb - 1) / nb;
-    t0 = (int64_t)lb * per;
-    t1 = t0 + per < ntiles ? t0 + per : ntiles;
+    t0 = (int64_t)lb * ntiles / nb;
+    t1 = (int64_t)(lb + 1) * ntiles / nb;
 }
 
 // ------------------------------------------------------ fixed-order reduce
