@@ -565,6 +565,73 @@ __device__ __forceinline__ R ell_row(int32_t cj, R aj, const R *__restrict__ x, 
     return acc;
 }
 
+// 16-byte pieces of a vertex-major row: V = 16 / sizeof(R) consecutive
+// columns, one dwordx4 access (the address must be 16-byte aligned).
+template <typename R>
+struct Piece {
+    static constexpr int V = 16 / (int)sizeof(R);
+    R v[V];
+};
+
+template <typename R>
+__device__ __forceinline__ Piece<R> ld_piece(const R *p) {
+    Piece<R> o;
+    if constexpr (sizeof(R) == 8) {
+        const double2 t = *reinterpret_cast<const double2 *>(p);
+        o.v[0] = t.x;
+        o.v[1] = t.y;
+    } else {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        o.v[0] = t.x;
+        o.v[1] = t.y;
+        o.v[2] = t.z;
+        o.v[3] = t.w;
+    }
+    return o;
+}
+
+template <typename R>
+__device__ __forceinline__ void st_piece(R *p, const Piece<R> &o) {
+    if constexpr (sizeof(R) == 8)
+        *reinterpret_cast<double2 *>(p) = make_double2(o.v[0], o.v[1]);
+    else
+        *reinterpret_cast<float4 *>(p) = make_float4(o.v[0], o.v[1], o.v[2], o.v[3]);
+}
+
+// One padded row (W <= 8 entries, loaded by ell_entry) times 8 columns of x
+// (k = 8, rows 16-byte aligned) for a group of 8 lanes, with 16-byte gathers:
+// lane q + LPR s (LPR = 8 / V lanes per x row) gathers columns [qV, qV + V)
+// of the entries s, s + NPI, s + 2 NPI, ... (NPI = 8 / LPR entries per
+// gather instruction), so a row takes 8 / NPI gathers instead of 8. The NPI
+// partial sums are added by a fixed xor tree; every lane of the group ends
+// with the row's columns [qV, qV + V), q = lane % LPR.
+template <typename R>
+__device__ __forceinline__ Piece<R> ell_row8_wide(int32_t cj, R aj, const R *__restrict__ x,
+                                                  int lane, int gbase) {
+    constexpr int V = Piece<R>::V, LPR = 8 / V, NPI = 8 / LPR, NS = 8 / NPI;
+    const int q = lane % LPR, sub = lane / LPR;
+    int32_t js[NS];
+    Piece<R> xv[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) js[s] = __shfl(cj, gbase + s * NPI + sub);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) xv[s] = ld_piece(x + (int64_t)js[s] * 8 + q * V);
+    Piece<R> acc;
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc.v[v] = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const R a = __shfl(aj, gbase + s * NPI + sub);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc.v[v] += a * xv[s].v[v];
+    }
+#pragma unroll
+    for (int off = LPR; off < 8; off *= 2)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc.v[v] += __shfl_xor(acc.v[v], off);
+    return acc;
+}
+
 // RU rows at once for one lane group, as row_apply without the mask: row u
 // is i[u] with entries [rb[u], rb[u] + len[u]) and dterm[u] on the diagonal
 // (PLAIN: the coefficients are the stored values as they are, beta and dterm

@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
 k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int32_t W,
           const int32_t *__restrict__ col, int32_t nV, const R *__restrict__ v,
           const R *__restrict__ dvec, int k, const R *__restrict__ r, R *__restrict__ w,
-          const CgCol *__restrict__ st, double *__restrict__ part) {
+          const CgCol *__restrict__ st, double *__restrict__ part, int wide) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = TR / G;
     __shared__ double s_part[kMaxK];
@@ -296,6 +296,41 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
     double dsum = 0.0;
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
+    if (ELL && KP == 8 && wide) {
+        // eight columns (k = 8) over padded rows of at most 8 entries, r and
+        // w 16-byte aligned: 16-byte gathers
+        constexpr int V = Piece<R>::V, LPR = 8 / V;
+        const int q = lane % LPR;
+        double ds[V];
+#pragma unroll
+        for (int c = 0; c < V; ++c) ds[c] = 0.0;
+        for (int64_t tile = t0; tile < t1; ++tile) {
+            const int64_t row = tile * GPB + grp;
+            if (row >= nV) break;  // uniform over the lane group; later tiles are past nV too
+            int32_t cj;
+            R aj;
+            ell_entry(col, v, W, (int32_t)row, lane, cj, aj);
+            const Piece<R> acc = ell_row8_wide<R>(cj, aj, r, lane, gbase);
+            if (lane < LPR) {
+                const int64_t e = row * 8 + q * V;
+                st_piece(w + e, acc);
+                const Piece<R> ri = ld_piece(r + e);
+                const R d = dvec[row];
+#pragma unroll
+                for (int c = 0; c < V; ++c) ds[c] += (double)acc.v[c] * (double)(d * ri.v[c]);
+            }
+        }
+        // column c's sum sits in lane c / V, component c % V
+        double dc = 0.0;
+#pragma unroll
+        for (int c = 0; c < V; ++c) {
+            const double t = __shfl(ds[c], gbase + lane / V);
+            if (lane % V == c) dc = t;
+        }
+        column_partials(&dc, 1, k, G, out_lane, s_red, s_part);
+        store_partials(s_part, k, part);
+        return;
+    }
     for (int64_t tile = t0; tile < t1; tile += RU) {
         int32_t i[RU], rb[RU], len[RU];
         bool ok[RU];
@@ -641,15 +676,16 @@ int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R 
     constexpr int G = KP < 8 ? 8 : KP;
     const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), kMaxRedBlocks);
     if (m->ell_w) {
+        const int wide = k == 8 && m->ell_w <= 8 && ((uintptr_t)r % 16) == 0 && ((uintptr_t)w % 16) == 0;
         auto kfn = k_cg_sdot<R, KP, true>;
         DGO_LAUNCH_EXT("cg_sdot", s, kfn, dim3(nb), dim3(TR), 0u, (const int2 *)nullptr,
                        (const uint8_t *)nullptr, m->ell_w, (const int32_t *)m->ell_col, m->nV, v, dvec,
-                       k, r, w, st, part);
+                       k, r, w, st, part, wide);
     } else {
         auto kfn = k_cg_sdot<R, KP, false>;
         DGO_LAUNCH_EXT("cg_sdot", s, kfn, dim3(nb), dim3(TR), 0u, (const int2 *)m->rdesc,
                        (const uint8_t *)m->rlen, 0, (const int32_t *)m->col, m->nV, v, dvec, k, r, w,
-                       st, part);
+                       st, part, 0);
     }
     return (int)nb;
 }
