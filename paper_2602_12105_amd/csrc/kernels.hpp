@@ -598,16 +598,18 @@ __device__ __forceinline__ void st_piece(R *p, const Piece<R> &o) {
         *reinterpret_cast<float4 *>(p) = make_float4(o.v[0], o.v[1], o.v[2], o.v[3]);
 }
 
-// One padded row (W <= 8 entries, loaded by ell_entry) times 8 columns of x
-// (k = 8, rows 16-byte aligned) for a group of 8 lanes, with 16-byte gathers:
-// lane q + LPR s (LPR = 8 / V lanes per x row) gathers columns [qV, qV + V)
-// of the entries s, s + NPI, s + 2 NPI, ... (NPI = 8 / LPR entries per
-// gather instruction), so a row takes 8 / NPI gathers instead of 8. The NPI
-// partial sums are added by a fixed xor tree; every lane of the group ends
-// with the row's columns [qV, qV + V), q = lane % LPR.
+// A row times 8 columns of x (k = 8, rows 16-byte aligned) for a group of 8
+// lanes, with 16-byte gathers. The row's entries come in chunks of 8, one
+// entry (cj, aj) per lane (unused lanes: a valid row and 0). In a chunk, lane
+// q + LPR s (LPR = 8 / V lanes per x row) gathers columns [qV, qV + V) of
+// entries s, s + NPI, s + 2 NPI, ... (NPI = 8 / LPR entries per gather
+// instruction), so a chunk takes 8 / NPI gathers instead of 8; wide8_chunk
+// adds them to the lane's partial sums, wide8_combine adds the NPI partial
+// sums by a fixed xor tree, after which every lane of the group holds the
+// row's columns [qV, qV + V), q = lane % LPR.
 template <typename R>
-__device__ __forceinline__ Piece<R> ell_row8_wide(int32_t cj, R aj, const R *__restrict__ x,
-                                                  int lane, int gbase) {
+__device__ __forceinline__ void wide8_chunk(int32_t cj, R aj, const R *__restrict__ x, int lane,
+                                            int gbase, Piece<R> &acc) {
     constexpr int V = Piece<R>::V, LPR = 8 / V, NPI = 8 / LPR, NS = 8 / NPI;
     const int q = lane % LPR, sub = lane / LPR;
     int32_t js[NS];
@@ -616,19 +618,31 @@ __device__ __forceinline__ Piece<R> ell_row8_wide(int32_t cj, R aj, const R *__r
     for (int s = 0; s < NS; ++s) js[s] = __shfl(cj, gbase + s * NPI + sub);
 #pragma unroll
     for (int s = 0; s < NS; ++s) xv[s] = ld_piece(x + (int64_t)js[s] * 8 + q * V);
-    Piece<R> acc;
-#pragma unroll
-    for (int v = 0; v < V; ++v) acc.v[v] = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const R a = __shfl(aj, gbase + s * NPI + sub);
 #pragma unroll
         for (int v = 0; v < V; ++v) acc.v[v] += a * xv[s].v[v];
     }
+}
+
+template <typename R>
+__device__ __forceinline__ void wide8_combine(Piece<R> &acc) {
+    constexpr int LPR = 8 / Piece<R>::V;
 #pragma unroll
     for (int off = LPR; off < 8; off *= 2)
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc.v[v] += __shfl_xor(acc.v[v], off);
+        for (int v = 0; v < Piece<R>::V; ++v) acc.v[v] += __shfl_xor(acc.v[v], off);
+}
+
+template <typename R>
+__device__ __forceinline__ Piece<R> ell_row8_wide(int32_t cj, R aj, const R *__restrict__ x,
+                                                  int lane, int gbase) {
+    Piece<R> acc;
+#pragma unroll
+    for (int v = 0; v < Piece<R>::V; ++v) acc.v[v] = R(0);
+    wide8_chunk(cj, aj, x, lane, gbase, acc);
+    wide8_combine(acc);
     return acc;
 }
 

@@ -170,15 +170,39 @@ def test_spmv_parity_long_rows(name, k):
     test_spmv_parity(name, k, "f64")
 
 
-def test_spmv_batch():
+@pytest.mark.parametrize("k", [4, 8])
+def test_spmv_batch(k):
     X, E, m = _mesh("ico3")
     Xb = torch.from_numpy(np.stack([X, 1.1 * X])).to(DEV)
     K, M = dgo.assemble(m, Xb)
-    x = torch.from_numpy(meshgen.normal(3, 2 * X.shape[0] * 4).reshape(2, -1, 4)).to(DEV)
+    x = torch.from_numpy(meshgen.normal(3, 2 * X.shape[0] * k).reshape(2, -1, k)).to(DEV)
     y = dgo.spmv(m, 1.0, M, 1e-3, K, x)
     for b in range(2):
         yb = dgo.spmv(m, 1.0, M[b].contiguous(), 1e-3, K[b].contiguous(), x[b].contiguous())
         assert torch.equal(yb, y[b])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmv_k8_unaligned(dtype):
+    """Eight columns at an address that is not 16-byte aligned take the
+    per-column gathers instead of the 16-byte ones; both match the oracle."""
+    print(f"[spmv-unaligned] ico5 k=8 {dtype}", flush=True)
+    X, E, m = _mesh("ico5")
+    td = torch.float64 if dtype == "f64" else torch.float32
+    K, M = dgo.assemble(m, torch.from_numpy(X).to(DEV, td))
+    x = meshgen.uniform(2, X.shape[0] * 8).reshape(-1, 8) * 2 - 1
+    buf = torch.empty(X.shape[0] * 8 + 1, dtype=td, device=DEV)
+    xu = buf[1:].view(-1, 8)
+    xu.copy_(torch.from_numpy(x).to(DEV, td))
+    assert xu.data_ptr() % 16 != 0
+    ya = dgo.spmv(m, 0.7, M, 1.3, K, xu.clone()).double().cpu().numpy()
+    yu = dgo.spmv(m, 0.7, M, 1.3, K, xu).double().cpu().numpy()
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    Kh, Mh, xh = K.double().cpu().numpy(), M.double().cpu().numpy(), xu.double().cpu().numpy()
+    yo = oracle.spmv(rp, col, 0.7, Mh, 1.3, Kh, xh).reshape(ya.shape)
+    sc = spmv_scale(rp, col, 0.7, Mh, 1.3, Kh, xh).reshape(ya.shape)
+    assert np.all(np.abs(ya - yo) <= RTOL[dtype] * sc)
+    assert np.all(np.abs(yu - yo) <= RTOL[dtype] * sc)
 
 
 def _cfg2_system(level, k, dtype, seed=1):
