@@ -135,8 +135,8 @@ def measured_traffic(kernel, dtype, level):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
-                                   "supported (the sharding design is described in DESIGN.md)",
+        print(json.dumps({"error": "the library runs on one GPU; runs on several GPUs are not "
+                                   "supported (the path is not sharded)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.cpu_baseline_suite:

@@ -60,7 +60,7 @@ typedef enum {
     DGO_ERR_DEVICE = 5,        /* a HIP runtime error */
     DGO_ERR_NOT_CONVERGED = 6, /* solver stopped early and strict was set */
     DGO_ERR_BUDGET = 7,        /* request larger than the server's HBM budget */
-    DGO_ERR_UNSUPPORTED = 8,   /* valid input outside what this build handles */
+    DGO_ERR_UNSUPPORTED = 8,   /* valid input outside what the library handles */
     DGO_ERR_TIMEOUT = 9,       /* a wait ran out of time */
     DGO_ERR_SHUTDOWN = 10      /* server is shutting down */
 } dgo_status;
