@@ -861,7 +861,9 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     // and a column that runs past the plan gets further chunks.
     dgo_mesh *mm = const_cast<dgo_mesh *>(m);
     if (!mm->poll_host) {
-        DGO_HIP(hipHostMalloc(&mm->poll_host, 2 * sizeof(CgCol) * kMaxK, hipHostMallocDefault));
+        // two polling slots, then the final state and true residuals
+        DGO_HIP(hipHostMalloc(&mm->poll_host, 3 * sizeof(CgCol) * kMaxK + sizeof(double) * kMaxK,
+                              hipHostMallocDefault));
         for (auto &e : mm->poll_ev) DGO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     CgCol *hpoll = (CgCol *)mm->poll_host;
@@ -922,7 +924,6 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     if (done_iters > 0)
         launch_fin<FIN_SR_ITER>(partU[done_iters & 1], (int)nb_v, part2, nbs, k,
                                 stt[(done_iters + 1) & 1], stt[done_iters & 1], prm, nullptr, s);
-    CgCol hst[kMaxK];
     if (ell)
         DGO_LAUNCH("cg_unorder", s,
                    k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, m->order, stt[done_iters & 1],
@@ -936,7 +937,11 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
                                                   mask, k, KP, beff, u, part));
     launch_fin<FIN_OUT>(part, (int)nb_t, nullptr, 0, k, nullptr, nullptr, prm, tr, s);
     DGO_HIP(hipGetLastError());
-    double htr[kMaxK];
+    // into pinned memory (a copy to pageable memory would block the host
+    // once per copy); a chunk still in flight wrote its polling slot earlier
+    // in stream order
+    CgCol *hst = hpoll + 2 * kMaxK;
+    double *htr = (double *)(hpoll + 3 * kMaxK);
     DGO_HIP(hipMemcpyAsync(hst, stt[done_iters & 1], sizeof(CgCol) * k, hipMemcpyDeviceToHost, s));
     DGO_HIP(hipMemcpyAsync(htr, tr, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     DGO_HIP(hipStreamSynchronize(s));
