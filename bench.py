@@ -85,10 +85,14 @@ def alg_bytes(kind, s, nV, nF, nnz, k):
     if kind == "assemble_vjp_tri":
         # X, gK, gM read, gX written, triangles
         return 3 * s * nV + 12 * nF + s * nnz + s * nV + 3 * s * nV
-    if kind in ("spmm", "cg_spmm_dot", "cg_sdot"):
+    if kind in ("spmm", "cg_sdot"):
         # CSR values + columns, row pointers, a diagonal (mass, or D^-1), x
         # read, y written
         return nnz * (s + 4) + 4 * (nV + 1) + s * nV + 2 * k * s * nV
+    if kind == "cg_start":
+        # A x0 as in the SpMM (x0 read), then beff and D^-1 read, r, p, s and
+        # the row-order copy of x0 written
+        return nnz * (s + 4) + 4 * (nV + 1) + s * nV + k * s * nV + k * s * nV + s * nV + 4 * k * s * nV
     if kind == "cg_vupdate":
         # read r w p s, write p s r, read D^-1; x (read and written) only in
         # every second iteration (two steps at once): 8 vectors on average

@@ -150,81 +150,55 @@ __global__ void k_solve_vjp(const int32_t *__restrict__ rowptr, const int32_t *_
 
 // ------------------------------------------------------------------- PCG
 
-// q = A_II p (q_B = 0), from M and K (A x0 at the start of a solve). With
-// part != NULL also stores per-column partial sums of p.q.
+// The start of a solve, one pass over the rows: q = A_II x0 (q_B = 0) from M
+// and K, then r = beff - q, p = s = 0, and partial sums of r.z, r.r and
+// beff.beff (z = D^-1 r). x0 and beff are in natural order; r, p, s and dvec
+// in the loop's order (with pos_order, the rows' positions, where xp
+// receives x0 as well; else natural).
 template <typename R, int KP, bool MASK>
-__global__ void __launch_bounds__(T, KP <= 16 ? 8 : 4)
-k_cg_spmm_dot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
-              const int32_t *__restrict__ col, int32_t nV, R alpha_m, const R *__restrict__ M,
-              R beta_k, const R *__restrict__ K, const uint8_t *__restrict__ mask, int k,
-              const R *__restrict__ p, R *__restrict__ q, double *__restrict__ part) {
+__global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
+k_cg_start(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
+           const int32_t *__restrict__ col, int32_t nV, R alpha_m, const R *__restrict__ M,
+           R beta_k, const R *__restrict__ K, const uint8_t *__restrict__ mask, int k,
+           const R *__restrict__ x0, const R *__restrict__ beff, int pos_order, R *__restrict__ xp,
+           const R *__restrict__ dvec, R *__restrict__ r, R *__restrict__ p, R *__restrict__ sv,
+           double *__restrict__ part) {
     constexpr int G = KP < 8 ? 8 : KP;
-    constexpr int GPB = T / G;
-    __shared__ double s_part[kMaxK];
-    __shared__ double s_red[red_scratch(T, 1)];
+    constexpr int GPB = TR / G;
+    __shared__ double s_part[3 * kMaxK];
+    __shared__ double s_red[red_scratch(TR, 3)];
     const int lane = threadIdx.x % G, grp = threadIdx.x / G;
     const int gbase = (threadIdx.x & 63) - lane;
     const bool out_lane = lane < k && lane < KP;
-    double dsum = 0.0;
+    double d[3] = {0.0, 0.0, 0.0};
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t r = tile * GPB + grp;
-        if (r >= nV) continue;  // uniform over the lane group
-        const int2 d = rdesc[r];
-        const int32_t i = d.x;
-        const int32_t len = rlen[r];
-        R acc = 0, pi = 0;
+        const int64_t pos = tile * GPB + grp;
+        if (pos >= nV) continue;  // uniform over the lane group
+        const int2 dd = rdesc[pos];
+        const int32_t i = dd.x;
+        const int32_t len = rlen[pos];
+        R q = 0;
         if (!(MASK && mask[i]))
-            acc = row_apply<R, G, KP, MASK>(col, K, beta_k, alpha_m * M[i], mask, p, i, d.y, len,
-                                            k, lane, gbase, &pi);
+            q = row_apply<R, G, KP, MASK>(col, K, beta_k, alpha_m * M[i], mask, x0, i, dd.y, len,
+                                          k, lane, gbase, nullptr);
         if (out_lane) {
-            const int64_t e = (int64_t)i * k + lane;
-            q[e] = acc;
-            if (part) {
-                if (G != KP) pi = p[e];  // row_apply returns p[i, c] only when G == KP
-                dsum += (double)pi * (double)acc;
-            }
+            const int64_t vi = pos_order ? pos : (int64_t)i;
+            const int64_t e = vi * k + lane, en = (int64_t)i * k + lane;
+            const R b = beff[en];
+            const R rv = b - q;
+            const R zv = dvec[vi] * rv;
+            if (xp) xp[e] = x0[en];
+            r[e] = rv;
+            p[e] = R(0);
+            sv[e] = R(0);
+            d[0] += (double)rv * (double)zv;
+            d[1] += (double)rv * (double)rv;
+            d[2] += (double)b * (double)b;
         }
     }
-    if (!part) return;
-    column_partials(&dsum, 1, k, G, out_lane, s_red, s_part);
-    store_partials(s_part, k, part);
-}
-
-// r = beff - q, p = s = 0; partial sums of r.z, r.r, beff.beff (z = D^-1 r).
-// With xp != NULL the solve runs in row order: position p takes row
-// order[p] (identity if order is NULL) of beff, q and x0 (copied to xp), and
-// dvec is D^-1 in row order.
-template <typename R>
-__global__ void __launch_bounds__(TR)
-k_cg_init(int32_t nV, int k, int KP, const int32_t *__restrict__ order,
-          const R *__restrict__ beff, const R *__restrict__ q, const R *__restrict__ x0,
-          R *__restrict__ xp, const R *__restrict__ dvec, R *__restrict__ r, R *__restrict__ p,
-          R *__restrict__ sv, double *__restrict__ part) {
-    __shared__ double s_part[3 * kMaxK];
-    __shared__ double s_red[red_scratch(TR, 3)];
-    const VLane L = vlane(k, KP);
-    double d[3] = {0.0, 0.0, 0.0};
-    int64_t t0, t1;
-    tile_range(((int64_t)nV + L.gpb - 1) / L.gpb, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t i = tile * L.gpb + L.grp;
-        if (i >= nV || !L.act) continue;
-        const int64_t e = i * k + L.c;
-        const int64_t en = (order ? (int64_t)order[i] : i) * k + L.c;
-        const R b = beff[en];
-        const R rv = b - q[en];
-        const R zv = dvec[i] * rv;
-        if (xp) xp[e] = x0[en];
-        r[e] = rv;
-        p[e] = R(0);
-        sv[e] = R(0);
-        d[0] += (double)rv * (double)zv;
-        d[1] += (double)rv * (double)rv;
-        d[2] += (double)b * (double)b;
-    }
-    column_partials(d, 3, k, KP, L.act, s_red, s_part);
+    column_partials(d, 3, k, G, out_lane, s_red, s_part);
     store_partials(s_part, 3 * k, part);
 }
 
@@ -624,6 +598,43 @@ k_cg_trueres(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col
     store_partials(s_part, k, part);
 }
 
+// The same true residual for FP64 solves, with the lane groups of the SpMV
+// kernels: rows in the mesh's row order, G lanes per row, the row's sum
+// (alpha M + beta K) u formed as row_apply does, then (beff - A u)^2 added
+// per column (the sum of a row is formed in a different order than above).
+template <typename R, int KP, bool MASK>
+__global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
+k_cg_trueres_rows(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
+                  const int32_t *__restrict__ col, int32_t nV, R alpha_m, const R *__restrict__ M,
+                  R beta_k, const R *__restrict__ K, const uint8_t *__restrict__ mask, int k,
+                  const R *__restrict__ beff, const R *__restrict__ u, double *__restrict__ part) {
+    constexpr int G = KP < 8 ? 8 : KP;
+    constexpr int GPB = TR / G;
+    __shared__ double s_part[kMaxK];
+    __shared__ double s_red[red_scratch(TR, 1)];
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int gbase = (threadIdx.x & 63) - lane;
+    const bool out_lane = lane < k && lane < KP;
+    double d = 0.0;
+    int64_t t0, t1;
+    tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t pos = tile * GPB + grp;
+        if (pos >= nV) continue;  // uniform over the lane group
+        const int2 dd = rdesc[pos];
+        const int32_t i = dd.x;
+        if (MASK && mask[i]) continue;
+        const R q = row_apply<R, G, KP, MASK>(col, K, beta_k, alpha_m * M[i], mask, u, i, dd.y,
+                                              (int32_t)rlen[pos], k, lane, gbase, nullptr);
+        if (out_lane) {
+            const double sres = (double)beff[(int64_t)i * k + lane] - (double)q;
+            d += sres * sres;
+        }
+    }
+    column_partials(&d, 1, k, G, out_lane, s_red, s_part);
+    store_partials(s_part, k, part);
+}
+
 unsigned nblocks_for(int64_t ntiles, int64_t cap = kMaxBlocks) {
     int64_t b = ntiles < cap ? ntiles : cap;
     return (unsigned)(b < 1 ? 1 : b);
@@ -660,35 +671,75 @@ void launch_spmm(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R beta, 
 
 // Returns the number of workgroups launched (the count of partial rows).
 template <typename R, int KP, bool MASK>
-int launch_cg_spmm_kp(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
-                      const uint8_t *mask, int k, const R *p, R *q, double *part, hipStream_t s) {
+int launch_cg_start_kp(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
+                       const uint8_t *mask, int k, const R *x0, const R *beff, int pos_order,
+                       R *xp, const R *dvec, R *r, R *p, R *sv, double *part, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
-    const unsigned nb = nblocks_for(ntiles(m->nV, T / G), part ? kMaxRedBlocks : kMaxBlocks);
-    DGO_LAUNCH("cg_spmm_dot", s,
-               k_cg_spmm_dot<R, KP, MASK><<<nb, T, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV, alpha,
-                                                           M, beta, K, mask, k, p, q, part));
+    const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), kMaxRedBlocks);
+    DGO_LAUNCH("cg_start", s,
+               k_cg_start<R, KP, MASK><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV, alpha, M,
+                                                        beta, K, mask, k, x0, beff, pos_order, xp,
+                                                        dvec, r, p, sv, part));
     return (int)nb;
 }
 
 template <typename R, bool MASK>
-int launch_cg_spmm_m(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
-                     const uint8_t *mask, int k, const R *p, R *q, double *part, hipStream_t s) {
+int launch_cg_start_m(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
+                      const uint8_t *mask, int k, const R *x0, const R *beff, int pos_order, R *xp,
+                      const R *dvec, R *r, R *p, R *sv, double *part, hipStream_t s) {
+#define DGO_START_CASE(KPV)                                                                        \
+    return launch_cg_start_kp<R, KPV, MASK>(m, alpha, M, beta, K, mask, k, x0, beff, pos_order, xp, \
+                                            dvec, r, p, sv, part, s)
     switch (pow2ceil(k)) {
-        case 1: return launch_cg_spmm_kp<R, 1, MASK>(m, alpha, M, beta, K, mask, k, p, q, part, s);
-        case 2: return launch_cg_spmm_kp<R, 2, MASK>(m, alpha, M, beta, K, mask, k, p, q, part, s);
-        case 4: return launch_cg_spmm_kp<R, 4, MASK>(m, alpha, M, beta, K, mask, k, p, q, part, s);
-        case 8: return launch_cg_spmm_kp<R, 8, MASK>(m, alpha, M, beta, K, mask, k, p, q, part, s);
-        case 16: return launch_cg_spmm_kp<R, 16, MASK>(m, alpha, M, beta, K, mask, k, p, q, part, s);
-        case 32: return launch_cg_spmm_kp<R, 32, MASK>(m, alpha, M, beta, K, mask, k, p, q, part, s);
-        default: return launch_cg_spmm_kp<R, 64, MASK>(m, alpha, M, beta, K, mask, k, p, q, part, s);
+        case 1: DGO_START_CASE(1);
+        case 2: DGO_START_CASE(2);
+        case 4: DGO_START_CASE(4);
+        case 8: DGO_START_CASE(8);
+        case 16: DGO_START_CASE(16);
+        case 32: DGO_START_CASE(32);
+        default: DGO_START_CASE(64);
     }
+#undef DGO_START_CASE
 }
 
 template <typename R>
-int launch_cg_spmm(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
-                   const uint8_t *mask, int k, const R *p, R *q, double *part, hipStream_t s) {
-    if (mask) return launch_cg_spmm_m<R, true>(m, alpha, M, beta, K, mask, k, p, q, part, s);
-    return launch_cg_spmm_m<R, false>(m, alpha, M, beta, K, mask, k, p, q, part, s);
+int launch_cg_start(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
+                    const uint8_t *mask, int k, const R *x0, const R *beff, int pos_order, R *xp,
+                    const R *dvec, R *r, R *p, R *sv, double *part, hipStream_t s) {
+    if (mask)
+        return launch_cg_start_m<R, true>(m, alpha, M, beta, K, mask, k, x0, beff, pos_order, xp,
+                                          dvec, r, p, sv, part, s);
+    return launch_cg_start_m<R, false>(m, alpha, M, beta, K, mask, k, x0, beff, pos_order, xp, dvec,
+                                       r, p, sv, part, s);
+}
+
+// Returns the number of workgroups launched (the count of partial rows).
+template <typename R, int KP, bool MASK>
+int launch_trueres_rows_kp(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
+                           const uint8_t *mask, int k, const R *beff, const R *u, double *part,
+                           hipStream_t s) {
+    constexpr int G = KP < 8 ? 8 : KP;
+    const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), kMaxRedBlocks);
+    DGO_LAUNCH("cg_trueres", s,
+               k_cg_trueres_rows<R, KP, MASK><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV,
+                                                               alpha, M, beta, K, mask, k, beff, u,
+                                                               part));
+    return (int)nb;
+}
+
+template <typename R, bool MASK>
+int launch_trueres_rows_m(const dgo_mesh *m, R alpha, const R *M, R beta, const R *K,
+                          const uint8_t *mask, int k, const R *beff, const R *u, double *part,
+                          hipStream_t s) {
+    switch (pow2ceil(k)) {
+        case 1: return launch_trueres_rows_kp<R, 1, MASK>(m, alpha, M, beta, K, mask, k, beff, u, part, s);
+        case 2: return launch_trueres_rows_kp<R, 2, MASK>(m, alpha, M, beta, K, mask, k, beff, u, part, s);
+        case 4: return launch_trueres_rows_kp<R, 4, MASK>(m, alpha, M, beta, K, mask, k, beff, u, part, s);
+        case 8: return launch_trueres_rows_kp<R, 8, MASK>(m, alpha, M, beta, K, mask, k, beff, u, part, s);
+        case 16: return launch_trueres_rows_kp<R, 16, MASK>(m, alpha, M, beta, K, mask, k, beff, u, part, s);
+        case 32: return launch_trueres_rows_kp<R, 32, MASK>(m, alpha, M, beta, K, mask, k, beff, u, part, s);
+        default: return launch_trueres_rows_kp<R, 64, MASK>(m, alpha, M, beta, K, mask, k, beff, u, part, s);
+    }
 }
 
 template <int MODE>
@@ -788,7 +839,6 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     CgCol *stt[2] = {(CgCol *)(ws + L.off_st), (CgCol *)(ws + L.off_st + st_stride)};
     double *part = partU[0];
     double *tr = (double *)(ws + L.off_tr);
-    const size_t total = L.total;
 
     CgParams prm;
     prm.rtol = o.rtol;
@@ -822,12 +872,10 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
                    k_cg_lift<R><<<grid_for(n, T), T, 0, s>>>(m->rowptr, m->col, (int32_t)nV, ra, M, rb,
                                                              K, mask, k, b, g, beff, u));
     // r0 = beff - A_II x0, p = s = 0, w0 = A D^-1 r0; alpha_0 = (r.z) / (w.z)
-    launch_cg_spmm<R>(m, ra, M, rb, K, mask, k, u, w, nullptr, s);
-    DGO_LAUNCH("cg_init", s,
-               k_cg_init<R><<<nb_v, TR, 0, s>>>((int32_t)nV, k, KP, ell ? m->order : nullptr, beff,
-                                                w, u, ell ? x : nullptr, dvec, r, p, sv, part));
+    const int nb_0 = launch_cg_start<R>(m, ra, M, rb, K, mask, k, u, beff, ell ? 1 : 0,
+                                        ell ? x : nullptr, dvec, r, p, sv, part, s);
     int nb_s = launch_sdot<R>(m, v, dvec, k, r, w, nullptr, part2, s);
-    launch_fin<FIN_SR_INIT>(part, (int)nb_v, part2, nb_s, k, nullptr, stt[0], prm, nullptr, s);
+    launch_fin<FIN_SR_INIT>(part, nb_0, part2, nb_s, k, nullptr, stt[0], prm, nullptr, s);
     DGO_HIP(hipGetLastError());
 
     const int every = o.fixed_iters ? (o.max_iter > 0 ? o.max_iter : 1)
@@ -932,10 +980,18 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
         DGO_LAUNCH("cg_unorder", s,
                    k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, nullptr, stt[done_iters & 1],
                                                                  p, x, x));
-    DGO_LAUNCH("cg_trueres", s,
-               k_cg_trueres<R><<<nb_t, TR, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta, K,
-                                                  mask, k, KP, beff, u, part));
-    launch_fin<FIN_OUT>(part, (int)nb_t, nullptr, 0, k, nullptr, nullptr, prm, tr, s);
+    // the true residual: FP64 solves with the SpMV's lane groups, FP32 ones
+    // with one thread per (row, column) accumulating in FP64
+    int nb_tr = (int)nb_t;
+    if constexpr (sizeof(R) == 8) {
+        nb_tr = mask ? launch_trueres_rows_m<R, true>(m, ra, M, rb, K, mask, k, beff, u, part, s)
+                     : launch_trueres_rows_m<R, false>(m, ra, M, rb, K, mask, k, beff, u, part, s);
+    } else {
+        DGO_LAUNCH("cg_trueres", s,
+                   k_cg_trueres<R><<<nb_t, TR, 0, s>>>(m->rowptr, m->col, (int32_t)nV, alpha, M, beta,
+                                                      K, mask, k, KP, beff, u, part));
+    }
+    launch_fin<FIN_OUT>(part, nb_tr, nullptr, 0, k, nullptr, nullptr, prm, tr, s);
     DGO_HIP(hipGetLastError());
     // into pinned memory (a copy to pageable memory would block the host
     // once per copy); a chunk still in flight wrote its polling slot earlier
