@@ -496,6 +496,9 @@ __device__ __forceinline__ R row_apply(const int32_t *__restrict__ col, const R 
         } else {
 #pragma unroll
             for (int s0 = 0; s0 < KP; s0 += CH) {
+                // one lane per entry (NP = 1): a chunk past the row's end
+                // holds only padding (coefficient 0), so it is skipped
+                if (NP == 1 && e0 + s0 >= len) break;
                 int32_t js[CH];
                 R xv[CH];
 #pragma unroll
@@ -535,7 +538,7 @@ __device__ __forceinline__ void ell_entry(const int32_t *__restrict__ col, const
 
 template <typename R, int G, int KP>
 __device__ __forceinline__ R ell_row(int32_t cj, R aj, const R *__restrict__ x, int32_t i, int k,
-                                     int lane, int gbase, R *xi) {
+                                     int32_t W, int lane, int gbase, R *xi) {
     constexpr int NP = G / KP;
     constexpr int CH = KP < 8 ? KP : 8;
     const int c = lane % KP, part = lane / KP;
@@ -546,6 +549,7 @@ __device__ __forceinline__ R ell_row(int32_t cj, R aj, const R *__restrict__ x, 
     } else {
 #pragma unroll
         for (int s0 = 0; s0 < KP; s0 += CH) {
+            if (NP == 1 && s0 >= W) break;  // only padding from here on
             int32_t js[CH];
             R xv[CH];
 #pragma unroll
@@ -697,6 +701,7 @@ __device__ __forceinline__ void rows_apply(const int32_t *__restrict__ col,
         } else {
 #pragma unroll
             for (int s0 = 0; s0 < KP; s0 += CH) {
+                if (NP == 1 && e0 + s0 >= lmax) break;  // only padding from here on
                 int32_t js[RU][CH];
                 R xv[RU][CH];
 #pragma unroll

@@ -193,7 +193,7 @@ __device__ __forceinline__ void sdot_unit(const SrvDesc &q, int32_t unit, double
             if (tile + 1 < te && row + GPB < nV) ell_entry(q.ell_col, q.v, W, row + GPB, lane, cj, aj);
             if (row >= nV) continue;  // uniform over the lane group
             R ri = 0;
-            const R acc = ell_row<R, G, KP>(cj0, aj0, q.r, row, q.k, lane, gbase, &ri);
+            const R acc = ell_row<R, G, KP>(cj0, aj0, q.r, row, q.k, W, lane, gbase, &ri);
             if (out_lane) {
                 const int64_t e = (int64_t)row * q.k + lane;
                 q.w[e] = acc;
