@@ -233,6 +233,24 @@ def test_pcg_fixed_iterations_match_oracle(dtype, iters):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pcg_k13_match_oracle(dtype):
+    """13 columns (lane groups of 16 over padded rows of 7 entries: the gather
+    chunk past the row's end is skipped), fixed iteration count, L6 (breadth-
+    first row order)."""
+    print(f"[pcg-k13] ico6 {dtype}", flush=True)
+    m, K, M, b = _cfg2_system(6, 13, dtype, seed=4)
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=25, fixed_iters=True)
+    assert rep["iters"] == [25] * 13
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    uo, _, _ = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3, K.double().cpu().numpy(),
+                          b.double().cpu().numpy(), rtol=0.0, max_iter=25)
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
+    assert err <= tol, err
+    assert max(rep["true_relres"]) < 1.0
+
+
 @pytest.mark.parametrize("name", ["fan40", "grid130fan"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_pcg_long_rows_match_oracle(name, dtype):
