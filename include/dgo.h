@@ -262,7 +262,9 @@ dgo_status dgo_face_divergence(const dgo_mesh *mesh, dgo_dtype dtype, const void
 /* y = (alpha M + beta K) x for `batch` operator instances and k columns:
  * d_Mdiag (batch x nV), d_Kvals (batch x nnz), d_x and d_y (batch x nV x k),
  * 1 <= k <= 64. d_y must not alias d_x. This is the operator application
- * repeated inside the solves of Sec. 5.2. */
+ * repeated inside the solves of Sec. 5.2. With beta == 0 the operator is the
+ * diagonal alpha M and y = (alpha M_i) x_i is formed without reading K (the
+ * same bits as the full product for finite x; d_Kvals must still be given). */
 dgo_status dgo_spmv(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch, double alpha,
                     const void *d_Mdiag, double beta, const void *d_Kvals, int32_t k,
                     const void *d_x, void *d_y, dgo_stream stream);

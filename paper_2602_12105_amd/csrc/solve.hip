@@ -118,6 +118,17 @@ k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     }
 }
 
+// y = (alpha M_i) x_i: the operator with beta = 0 (a diagonal), one thread
+// per entry of batch x nV x k.
+template <typename R>
+__global__ void k_diag_apply(int64_t n, int k, R alpha, const R *__restrict__ M,
+                             const R *__restrict__ x, R *__restrict__ y) {
+    const int64_t e = (int64_t)blockIdx.x * T + threadIdx.x;
+    if (e >= n) return;
+    const int64_t row = e / k;  // batch * nV + vertex
+    y[e] = (alpha * M[row]) * x[e];
+}
+
 // Gradients of a linear solve with respect to K and M (see
 // dgo_linear_solve_vjp): one thread per row, sums over the columns c in
 // ascending order.
@@ -1039,6 +1050,21 @@ extern "C" dgo_status dgo_spmv(const dgo_mesh *m, dgo_dtype dtype, int32_t batch
     if (!m->rdesc || !m->rlen)
         return fail(DGO_ERR_INVALID_ARG, "dgo_spmv: mesh was built without SpMV row descriptors");
     hipStream_t s = (hipStream_t)stream;
+    if (beta == 0.0) {  // the diagonal alpha M: no pass over K
+        const int64_t n = (int64_t)batch * m->nV * k;
+        if (dtype == DGO_F64)
+            DGO_LAUNCH("spmm_diag", s,
+                       k_diag_apply<double><<<grid_for(n, T), T, 0, s>>>(
+                           n, k, alpha, (const double *)d_Mdiag, (const double *)d_x,
+                           (double *)d_y));
+        else
+            DGO_LAUNCH("spmm_diag", s,
+                       k_diag_apply<float><<<grid_for(n, T), T, 0, s>>>(
+                           n, k, (float)alpha, (const float *)d_Mdiag, (const float *)d_x,
+                           (float *)d_y));
+        DGO_HIP(hipGetLastError());
+        return DGO_OK;
+    }
     if (dtype == DGO_F64)
         launch_spmm<double>(m, batch, alpha, (const double *)d_Mdiag, beta, (const double *)d_Kvals, k,
                             (const double *)d_x, (double *)d_y, s);

@@ -183,6 +183,25 @@ def test_spmv_batch(k):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("k", [1, 8])
+def test_spmv_beta_zero_is_the_diagonal(dtype, k):
+    """beta = 0 applies alpha M without reading K: bit for bit (alpha M_i) x_i,
+    in a batch too, and the oracle's product to rounding."""
+    print(f"[spmv-diag] ico5 k={k} {dtype}", flush=True)
+    X, E, m = _mesh("ico5")
+    td = torch.float64 if dtype == "f64" else torch.float32
+    Xb = torch.from_numpy(np.stack([X, 1.1 * X])).to(DEV, td)
+    K, M = dgo.assemble(m, Xb)
+    x = torch.from_numpy(meshgen.normal(7, 2 * X.shape[0] * k).reshape(2, -1, k)).to(DEV, td)
+    y = dgo.spmv(m, 0.7, M, 0.0, K, x)
+    assert torch.equal(y, (0.7 * M)[:, :, None] * x)
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    yo = oracle.spmv(rp, col, 0.7, M[1].double().cpu().numpy(), 0.0, K[1].double().cpu().numpy(),
+                     x[1].double().cpu().numpy()).reshape(-1, k)
+    assert np.allclose(y[1].double().cpu().numpy(), yo, rtol=RTOL[dtype], atol=0.0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_spmv_k8_unaligned(dtype):
     """Eight columns at an address that is not 16-byte aligned take the
     per-column gathers instead of the 16-byte ones; both match the oracle."""
