@@ -317,12 +317,17 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
         double ds[V];
 #pragma unroll
         for (int c = 0; c < V; ++c) ds[c] = 0.0;
+        // the next tile's entries are loaded while this tile's gathers are in
+        // flight (measured faster once each workgroup had five tiles or so)
+        int32_t cjn = 0;
+        R ajn = R(0);
+        if (t0 < t1 && t0 * GPB + grp < nV) ell_entry(col, v, W, (int32_t)(t0 * GPB + grp), lane, cjn, ajn);
         for (int64_t tile = t0; tile < t1; ++tile) {
             const int64_t row = tile * GPB + grp;
             if (row >= nV) break;  // uniform over the lane group; later tiles are past nV too
-            int32_t cj;
-            R aj;
-            ell_entry(col, v, W, (int32_t)row, lane, cj, aj);
+            const int32_t cj = cjn;
+            const R aj = ajn;
+            if (tile + 1 < t1 && row + GPB < nV) ell_entry(col, v, W, (int32_t)(row + GPB), lane, cjn, ajn);
             const Piece<R> acc = ell_row8_wide<R>(cj, aj, r, lane, gbase);
             if (lane < LPR) {
                 const int64_t e = row * 8 + q * V;
