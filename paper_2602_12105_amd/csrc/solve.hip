@@ -766,17 +766,19 @@ void launch_fin(const double *part, int nblk, const double *part2, int nblk2, in
                                                         prm, out));
 }
 
-// w = A z runs on at most one 1024-thread workgroup per CU: with balanced
-// tile shares this was measured faster than two (2.49 vs 2.55 ms per L7 step;
-// 128 or 384 workgroups: 2.89 / 2.67 ms), and the next update then adds half
-// as many partial sums
+// w = A z with 8 or more columns runs on at most one 1024-thread workgroup
+// per CU: with balanced tile shares this was measured faster than two (2.49
+// vs 2.55 ms per L7 step; 128 or 384 workgroups: 2.89 / 2.67 ms), and the next
+// update then adds half as many partial sums. Fewer columns make cheap rows,
+// which want the two (the Dirichlet solve on the Kuhn cube 64^3, one column:
+// 4.98 vs 5.57 ms).
 constexpr int kSdotBlocks = 256;
 
 template <typename R, int KP>
 int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R *r, R *w,
                    const CgCol *st, double *part, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
-    const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), kSdotBlocks);
+    const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), KP >= 8 ? kSdotBlocks : kMaxRedBlocks);
     if (m->ell_w) {
         const int wide = k == 8 && m->ell_w <= 8 && ((uintptr_t)r % 16) == 0 && ((uintptr_t)w % 16) == 0;
         auto kfn = k_cg_sdot<R, KP, true>;
