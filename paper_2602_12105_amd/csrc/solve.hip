@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(T, KP <= 16 ? 8 : 4)
 k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
        const int32_t *__restrict__ col, int32_t nV, int64_t nnz, R alpha,
        const R *__restrict__ M, R beta, const R *__restrict__ K, int k, const R *__restrict__ x,
-       R *__restrict__ y, int wide) {
+       R *__restrict__ y) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = T / G;
     const int64_t bt = blockIdx.y;
@@ -68,34 +68,6 @@ k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     constexpr int RU = KP <= 8 ? kSpmvRows : 1;
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
-    if (KP == 8 && wide) {
-        // k = 8 with x and y 16-byte aligned: 16-byte gathers
-        constexpr int V = Piece<R>::V, LPR = 8 / V;
-        for (int64_t tile = t0; tile < t1; ++tile) {
-            const int64_t r = tile * GPB + grp;
-            if (r >= nV) break;  // uniform over the lane group; later tiles are past nV too
-            const int2 d = rdesc[r];
-            const int32_t i = d.x, len = rlen[r];
-            const R dt = alpha * M[i];
-            Piece<R> acc;
-#pragma unroll
-            for (int c = 0; c < V; ++c) acc.v[c] = R(0);
-            for (int32_t e0 = 0; e0 < len; e0 += 8) {
-                int32_t cj = i;
-                R aj = R(0);
-                if (e0 + lane < len) {
-                    const int32_t e = d.y + e0 + lane;
-                    cj = col[e];
-                    aj = beta * K[e];
-                    if (cj == i) aj += dt;
-                }
-                wide8_chunk(cj, aj, x, lane, gbase, acc);
-            }
-            wide8_combine(acc);
-            if (lane < LPR) st_piece(y + (int64_t)i * 8 + (lane % LPR) * V, acc);
-        }
-        return;
-    }
     for (int64_t tile = t0; tile < t1; tile += RU) {
         int32_t i[RU], rb[RU], len[RU];
         bool ok[RU];
@@ -127,6 +99,102 @@ __global__ void k_diag_apply(int64_t n, int k, R alpha, const R *__restrict__ M,
     if (e >= n) return;
     const int64_t row = e / k;  // batch * nV + vertex
     y[e] = (alpha * M[row]) * x[e];
+}
+
+// The SpMM with 8 columns and 16-byte aligned x, y: 16-byte gathers (two
+// FP64 or four FP32 columns per lane, see wide8_chunk) on 1024-thread
+// workgroups, each walking its tiles in a two-stage software pipeline: while
+// a tile's gathers are in flight, the next tile's row descriptor has arrived
+// and its first eight entries are loaded, and the descriptor of the tile
+// after that is loaded.
+template <typename R>
+__global__ void __launch_bounds__(TR)
+k_spmm8_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
+             const int32_t *__restrict__ col, int32_t nV, int64_t nnz, R alpha,
+             const R *__restrict__ M, R beta, const R *__restrict__ K, const R *__restrict__ x,
+             R *__restrict__ y) {
+    constexpr int G = 8, GPB = TR / G;
+    constexpr int V = Piece<R>::V, LPR = 8 / V;
+    const int64_t bt = blockIdx.y;
+    M += bt * nV;
+    K += bt * nnz;
+    x += bt * (int64_t)nV * 8;
+    y += bt * (int64_t)nV * 8;
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    const int gbase = (threadIdx.x & 63) - lane;
+    int64_t t0, t1;
+    tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
+    // the lane group's row of a tile (len 0: none; a row holds at least its diagonal)
+    auto desc = [&](int64_t tile, int2 &d, int32_t &len) {
+        const int64_t r = tile * GPB + grp;
+        d = make_int2(0, 0);
+        len = 0;
+        if (tile < t1 && r < nV) {
+            d = rdesc[r];
+            len = rlen[r];
+        }
+    };
+    // the lane's entry of a row's first eight and the row's mass
+    auto first = [&](const int2 &d, int32_t len, int32_t &cj, R &kv, R &mv) {
+        cj = d.x;
+        kv = R(0);
+        mv = R(0);
+        if (len > 0) {
+            mv = M[d.x];
+            if (lane < len) {
+                cj = col[d.y + lane];
+                kv = K[d.y + lane];
+            }
+        }
+    };
+    int2 dA, dB;
+    int32_t lA, lB;
+    desc(t0, dA, lA);
+    desc(t0 + 1, dB, lB);
+    int32_t cjA;
+    R kA, mA;
+    first(dA, lA, cjA, kA, mA);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        if (lA == 0) break;  // past nV: uniform over the lane group, and so are later tiles
+        int2 dC;
+        int32_t lC, cjB;
+        R kB, mB;
+        desc(tile + 2, dC, lC);
+        first(dB, lB, cjB, kB, mB);
+        const int32_t i = dA.x;
+        const R dt = alpha * mA;
+        Piece<R> acc;
+#pragma unroll
+        for (int c = 0; c < V; ++c) acc.v[c] = R(0);
+        {
+            R aj = R(0);
+            if (lane < lA) {
+                aj = beta * kA;
+                if (cjA == i) aj += dt;
+            }
+            wide8_chunk(cjA, aj, x, lane, gbase, acc);
+        }
+        for (int32_t e0 = 8; e0 < lA; e0 += 8) {  // rows of more than eight entries
+            int32_t cj = i;
+            R aj = R(0);
+            if (e0 + lane < lA) {
+                const int32_t e = dA.y + e0 + lane;
+                cj = col[e];
+                aj = beta * K[e];
+                if (cj == i) aj += dt;
+            }
+            wide8_chunk(cj, aj, x, lane, gbase, acc);
+        }
+        wide8_combine(acc);
+        if (lane < LPR) st_piece(y + (int64_t)i * 8 + (lane % LPR) * V, acc);
+        dA = dB;
+        lA = lB;
+        cjA = cjB;
+        kA = kB;
+        mA = mB;
+        dB = dC;
+        lB = lC;
+    }
 }
 
 // Gradients of a linear solve with respect to K and M (see
@@ -664,11 +732,22 @@ template <typename R, int KP>
 void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R beta, const R *K,
                     int k, const R *x, R *y, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
+    const int wide = KP == 8 && k == 8 && ((uintptr_t)x % 16) == 0 && ((uintptr_t)y % 16) == 0;
+    if (wide) {
+        // about five tiles per workgroup, and no fewer than one workgroup per
+        // CU (L7: 256 workgroups, 10.2 vs 14.1 us for the k_spmm grid; L9:
+        // 4096, 201 vs 206 us; 256 at L9, 80 tiles each: 267 us)
+        const int64_t nt8 = ntiles(m->nV, TR / 8);
+        dim3 grid8(nblocks_for(nt8, std::max<int64_t>(256, nt8 / 5)), (unsigned)batch);
+        auto kfn8 = k_spmm8_pipe<R>;
+        DGO_LAUNCH_EXT("spmm", s, kfn8, grid8, dim3(TR), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
+                       alpha, M, beta, K, x, y);
+        return;
+    }
     dim3 grid(nblocks_for(ntiles(m->nV, T / G)), (unsigned)batch);
     auto kfn = k_spmm<R, KP>;
-    const int wide = KP == 8 && k == 8 && ((uintptr_t)x % 16) == 0 && ((uintptr_t)y % 16) == 0;
     DGO_LAUNCH_EXT("spmm", s, kfn, grid, dim3(T), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
-                   alpha, M, beta, K, k, x, y, wide);
+                   alpha, M, beta, K, k, x, y);
 }
 
 template <typename R>
