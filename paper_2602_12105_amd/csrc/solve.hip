@@ -197,6 +197,94 @@ k_spmm8_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     }
 }
 
+// The same pipeline for one column: a lane per entry gathers x[j], and the
+// group's eight lanes are added by the shuffle tree of k_spmm (the same
+// operations in the same order as k_spmm's row for k = 1).
+template <typename R>
+__global__ void __launch_bounds__(TR)
+k_spmm1_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
+             const int32_t *__restrict__ col, int32_t nV, int64_t nnz, R alpha,
+             const R *__restrict__ M, R beta, const R *__restrict__ K, const R *__restrict__ x,
+             R *__restrict__ y) {
+    constexpr int G = 8, GPB = TR / G;
+    const int64_t bt = blockIdx.y;
+    M += bt * nV;
+    K += bt * nnz;
+    x += bt * (int64_t)nV;
+    y += bt * (int64_t)nV;
+    const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+    int64_t t0, t1;
+    tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
+    auto desc = [&](int64_t tile, int2 &d, int32_t &len) {
+        const int64_t r = tile * GPB + grp;
+        d = make_int2(0, 0);
+        len = 0;
+        if (tile < t1 && r < nV) {
+            d = rdesc[r];
+            len = rlen[r];
+        }
+    };
+    auto first = [&](const int2 &d, int32_t len, int32_t &cj, R &kv, R &mv) {
+        cj = d.x;
+        kv = R(0);
+        mv = R(0);
+        if (len > 0) {
+            mv = M[d.x];
+            if (lane < len) {
+                cj = col[d.y + lane];
+                kv = K[d.y + lane];
+            }
+        }
+    };
+    int2 dA, dB;
+    int32_t lA, lB;
+    desc(t0, dA, lA);
+    desc(t0 + 1, dB, lB);
+    int32_t cjA;
+    R kA, mA;
+    first(dA, lA, cjA, kA, mA);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        if (lA == 0) break;  // past nV: uniform over the lane group, and so are later tiles
+        int2 dC;
+        int32_t lC, cjB;
+        R kB, mB;
+        desc(tile + 2, dC, lC);
+        first(dB, lB, cjB, kB, mB);
+        const int32_t i = dA.x;
+        const R dt = alpha * mA;
+        R acc = 0;
+        {
+            R aj = R(0);
+            if (lane < lA) {
+                aj = beta * kA;
+                if (cjA == i) aj += dt;
+            }
+            acc += aj * x[cjA];
+        }
+        for (int32_t e0 = 8; e0 < lA; e0 += 8) {  // rows of more than eight entries
+            int32_t cj = i;
+            R aj = R(0);
+            if (e0 + lane < lA) {
+                const int32_t e = dA.y + e0 + lane;
+                cj = col[e];
+                aj = beta * K[e];
+                if (cj == i) aj += dt;
+            }
+            acc += aj * x[cj];
+        }
+#pragma unroll
+        for (int off = G / 2; off >= 1; off /= 2) acc += __shfl_down(acc, off, G);
+        if (lane == 0) y[i] = acc;
+        dA = dB;
+        lA = lB;
+        cjA = cjB;
+        kA = kB;
+        mA = mB;
+        dB = dC;
+        lB = lC;
+    }
+}
+
 // Gradients of a linear solve with respect to K and M (see
 // dgo_linear_solve_vjp): one thread per row, sums over the columns c in
 // ascending order.
@@ -741,6 +829,14 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
         dim3 grid8(nblocks_for(nt8, std::max<int64_t>(256, nt8 / 5)), (unsigned)batch);
         auto kfn8 = k_spmm8_pipe<R>;
         DGO_LAUNCH_EXT("spmm", s, kfn8, grid8, dim3(TR), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
+                       alpha, M, beta, K, x, y);
+        return;
+    }
+    if (KP == 1) {  // one column: the same pipeline, a lane per entry
+        const int64_t nt1 = ntiles(m->nV, TR / 8);
+        dim3 grid1(nblocks_for(nt1, std::max<int64_t>(256, nt1 / 5)), (unsigned)batch);
+        auto kfn1 = k_spmm1_pipe<R>;
+        DGO_LAUNCH_EXT("spmm", s, kfn1, grid1, dim3(TR), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
                        alpha, M, beta, K, x, y);
         return;
     }
