@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(T, KP <= 16 ? 8 : 4)
 k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
        const int32_t *__restrict__ col, int32_t nV, int64_t nnz, R alpha,
        const R *__restrict__ M, R beta, const R *__restrict__ K, int k, const R *__restrict__ x,
-       R *__restrict__ y) {
+       R *__restrict__ y, int wide) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = T / G;
     const int64_t bt = blockIdx.y;
@@ -68,6 +68,34 @@ k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     constexpr int RU = KP <= 8 ? kSpmvRows : 1;
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
+    if (KP == 8 && wide) {
+        // k = 8 with x and y 16-byte aligned: 16-byte gathers
+        constexpr int V = Piece<R>::V, LPR = 8 / V;
+        for (int64_t tile = t0; tile < t1; ++tile) {
+            const int64_t r = tile * GPB + grp;
+            if (r >= nV) break;  // uniform over the lane group; later tiles are past nV too
+            const int2 d = rdesc[r];
+            const int32_t i = d.x, len = rlen[r];
+            const R dt = alpha * M[i];
+            Piece<R> acc;
+#pragma unroll
+            for (int c = 0; c < V; ++c) acc.v[c] = R(0);
+            for (int32_t e0 = 0; e0 < len; e0 += 8) {
+                int32_t cj = i;
+                R aj = R(0);
+                if (e0 + lane < len) {
+                    const int32_t e = d.y + e0 + lane;
+                    cj = col[e];
+                    aj = beta * K[e];
+                    if (cj == i) aj += dt;
+                }
+                wide8_chunk(cj, aj, x, lane, gbase, acc);
+            }
+            wide8_combine(acc);
+            if (lane < LPR) st_piece(y + (int64_t)i * 8 + (lane % LPR) * V, acc);
+        }
+        return;
+    }
     for (int64_t tile = t0; tile < t1; tile += RU) {
         int32_t i[RU], rb[RU], len[RU];
         bool ok[RU];
@@ -821,7 +849,11 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
                     int k, const R *x, R *y, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
     const int wide = KP == 8 && k == 8 && ((uintptr_t)x % 16) == 0 && ((uintptr_t)y % 16) == 0;
-    if (wide) {
+    // the pipelines prefetch a row's first eight entries: used when every row
+    // fits them (triangle meshes); longer rows (tetrahedra) were measured
+    // faster in k_spmm (Kuhn cube 64^3, one column: 19.2 vs 26.6 us)
+    const bool short_rows = m->max_row <= 8;
+    if (wide && short_rows) {
         // about five tiles per workgroup, and no fewer than one workgroup per
         // CU (L7: 256 workgroups, 10.2 vs 14.1 us for the k_spmm grid; L9:
         // 4096, 201 vs 206 us; 256 at L9, 80 tiles each: 267 us)
@@ -832,7 +864,7 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
                        alpha, M, beta, K, x, y);
         return;
     }
-    if (KP == 1) {  // one column: the same pipeline, a lane per entry
+    if (KP == 1 && short_rows) {  // one column: the same pipeline, a lane per entry
         const int64_t nt1 = ntiles(m->nV, TR / 8);
         dim3 grid1(nblocks_for(nt1, std::max<int64_t>(256, nt1 / 5)), (unsigned)batch);
         auto kfn1 = k_spmm1_pipe<R>;
@@ -843,7 +875,7 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
     dim3 grid(nblocks_for(ntiles(m->nV, T / G)), (unsigned)batch);
     auto kfn = k_spmm<R, KP>;
     DGO_LAUNCH_EXT("spmm", s, kfn, grid, dim3(T), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
-                   alpha, M, beta, K, k, x, y);
+                   alpha, M, beta, K, k, x, y, wide);
 }
 
 template <typename R>
