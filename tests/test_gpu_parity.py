@@ -170,7 +170,7 @@ def test_spmv_parity_long_rows(name, k):
     test_spmv_parity(name, k, "f64")
 
 
-@pytest.mark.parametrize("k", [4, 8])
+@pytest.mark.parametrize("k", [1, 4, 8])
 def test_spmv_batch(k):
     X, E, m = _mesh("ico3")
     Xb = torch.from_numpy(np.stack([X, 1.1 * X])).to(DEV)
