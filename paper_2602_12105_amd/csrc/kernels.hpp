@@ -639,14 +639,48 @@ __device__ __forceinline__ void wide8_combine(Piece<R> &acc) {
         for (int v = 0; v < Piece<R>::V; ++v) acc.v[v] += __shfl_xor(acc.v[v], off);
 }
 
-template <typename R>
-__device__ __forceinline__ Piece<R> ell_row8_wide(int32_t cj, R aj, const R *__restrict__ x,
-                                                  int lane, int gbase) {
+// A padded row of W <= 8 entries (loaded by ell_entry, one per lane of the
+// KPW-lane group) times KPW = 8 or 16 columns of x (k = KPW, rows 16-byte
+// aligned), with 16-byte gathers: lane q + LPR s (LPR = KPW / V lanes per x
+// row) gathers columns [qV, qV + V) of entries s, s + NPI, ... (NPI = KPW /
+// LPR entries per instruction); with 16 columns, instructions past the W
+// real entries (only padding) are skipped. The NPI partial sums are added by a
+// fixed xor tree;
+// every lane of the group ends with the row's columns [qV, qV + V), q =
+// lane % LPR. For KPW = 8 these are wide8_chunk's operations in its order.
+template <typename R, int KPW>
+__device__ __forceinline__ Piece<R> ell_row_wide(int32_t cj, R aj, const R *__restrict__ x,
+                                                 int lane, int gbase, int32_t W) {
+    constexpr int V = Piece<R>::V, LPR = KPW / V, NPI = KPW / LPR, NS = KPW / NPI;
+    const int q = lane % LPR, sub = lane / LPR;
+    // instructions with real entries (uniform over the group); with 8 columns
+    // all are issued (a guard there slowed the 8-column iteration by 2%)
+    const int ns = KPW == 8 ? NS : (W + NPI - 1) / NPI;
+    int32_t js[NS];
+    Piece<R> xv[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        js[s] = __shfl(cj, gbase + s * NPI + sub);
+#pragma unroll
+        for (int v = 0; v < V; ++v) xv[s].v[v] = R(0);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (s < ns) xv[s] = ld_piece(x + (int64_t)js[s] * KPW + q * V);
     Piece<R> acc;
 #pragma unroll
-    for (int v = 0; v < Piece<R>::V; ++v) acc.v[v] = R(0);
-    wide8_chunk(cj, aj, x, lane, gbase, acc);
-    wide8_combine(acc);
+    for (int v = 0; v < V; ++v) acc.v[v] = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (s >= ns) break;
+        const R a = __shfl(aj, gbase + s * NPI + sub);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc.v[v] += a * xv[s].v[v];
+    }
+#pragma unroll
+    for (int off = LPR; off < KPW; off *= 2)
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc.v[v] += __shfl_xor(acc.v[v], off);
     return acc;
 }
 

@@ -493,10 +493,11 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
     double dsum = 0.0;
     int64_t t0, t1;
     tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
-    if (ELL && KP == 8 && wide) {
-        // eight columns (k = 8) over padded rows of at most 8 entries, r and
-        // w 16-byte aligned: 16-byte gathers
-        constexpr int V = Piece<R>::V, LPR = 8 / V;
+    if constexpr (ELL && (KP == 8 || KP == 16)) {
+      if (wide) {
+        // k = KP = 8 or 16 columns over padded rows of at most 8 entries, r
+        // and w 16-byte aligned: 16-byte gathers
+        constexpr int V = Piece<R>::V, LPR = KP / V;
         const int q = lane % LPR;
         double ds[V];
 #pragma unroll
@@ -512,9 +513,9 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
             const int32_t cj = cjn;
             const R aj = ajn;
             if (tile + 1 < t1 && row + GPB < nV) ell_entry(col, v, W, (int32_t)(row + GPB), lane, cjn, ajn);
-            const Piece<R> acc = ell_row8_wide<R>(cj, aj, r, lane, gbase);
+            const Piece<R> acc = ell_row_wide<R, KP>(cj, aj, r, lane, gbase, W);
             if (lane < LPR) {
-                const int64_t e = row * 8 + q * V;
+                const int64_t e = row * KP + q * V;
                 st_piece(w + e, acc);
                 const Piece<R> ri = ld_piece(r + e);
                 const R d = dvec[row];
@@ -532,6 +533,7 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
         column_partials(&dc, 1, k, G, out_lane, s_red, s_part);
         store_partials(s_part, k, part);
         return;
+      }
     }
     for (int64_t tile = t0; tile < t1; tile += RU) {
         int32_t i[RU], rb[RU], len[RU];
@@ -987,7 +989,8 @@ int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R 
     constexpr int G = KP < 8 ? 8 : KP;
     const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), KP >= 8 ? kSdotBlocks : kMaxRedBlocks);
     if (m->ell_w) {
-        const int wide = k == 8 && m->ell_w <= 8 && ((uintptr_t)r % 16) == 0 && ((uintptr_t)w % 16) == 0;
+        const int wide = (KP == 8 || KP == 16) && k == KP && m->ell_w <= 8 && ((uintptr_t)r % 16) == 0 &&
+                         ((uintptr_t)w % 16) == 0;
         auto kfn = k_cg_sdot<R, KP, true>;
         DGO_LAUNCH_EXT("cg_sdot", s, kfn, dim3(nb), dim3(TR), 0u, (const int2 *)nullptr,
                        (const uint8_t *)nullptr, m->ell_w, (const int32_t *)m->ell_col, m->nV, v, dvec,

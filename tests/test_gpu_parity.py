@@ -253,14 +253,15 @@ def test_pcg_fixed_iterations_match_oracle(dtype, iters):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_pcg_k13_match_oracle(dtype):
-    """13 columns (lane groups of 16 over padded rows of 7 entries: the gather
-    chunk past the row's end is skipped), fixed iteration count, L6 (breadth-
-    first row order)."""
-    print(f"[pcg-k13] ico6 {dtype}", flush=True)
-    m, K, M, b = _cfg2_system(6, 13, dtype, seed=4)
+@pytest.mark.parametrize("k", [13, 16])
+def test_pcg_k13_match_oracle(dtype, k):
+    """13 or 16 columns (lane groups of 16 over padded rows of 7 entries: the
+    gather chunk past the row's end is skipped; with 16, the 16-byte gathers),
+    fixed iteration count, L6 (breadth-first row order)."""
+    print(f"[pcg-k{k}] ico6 {dtype}", flush=True)
+    m, K, M, b = _cfg2_system(6, k, dtype, seed=4)
     u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=25, fixed_iters=True)
-    assert rep["iters"] == [25] * 13
+    assert rep["iters"] == [25] * k
     rp, col = [t.cpu().numpy() for t in m.csr()]
     uo, _, _ = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3, K.double().cpu().numpy(),
                           b.double().cpu().numpy(), rtol=0.0, max_iter=25)
