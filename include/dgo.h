@@ -113,7 +113,10 @@ dgo_status dgo_mesh_create(int32_t dim, int32_t nV, int64_t n_elem, const int32_
  * stream). NULL is accepted. */
 void dgo_mesh_destroy(dgo_mesh *mesh);
 
-/* Host-side sizes; no device work. */
+/* Sizes of the mesh's simplex sets and operators (the element, edge and
+ * vertex counts of the simplex hierarchy, Sec. 4.1 and 6.1, and the nonzero
+ * count of the vertex-indexed operators of Sec. 5.1), read on the host: no
+ * device work, no synchronisation. DGO_ERR_INVALID_ARG for NULL arguments. */
 dgo_status dgo_mesh_sizes(const dgo_mesh *mesh, dgo_sizes *out);
 
 /* Copy out the edge topology (any pointer may be NULL to skip it):
@@ -125,7 +128,11 @@ dgo_status dgo_mesh_sizes(const dgo_mesh *mesh, dgo_sizes *out);
 dgo_status dgo_mesh_edges(const dgo_mesh *mesh, int32_t *d_EV, int32_t *d_elem_edge,
                           int8_t *d_elem_sign, dgo_stream stream);
 
-/* Copy out the CSR pattern: d_rowptr (nV + 1), d_col (nnz). Either may be NULL. */
+/* Copy out the CSR pattern of the vertex-indexed operators: the diagonal and
+ * the vertex adjacency VV (Sec. 4.1; the vertex_adjacency of the ARAP
+ * example, Sec. 4.2), rows sorted by column. d_rowptr (nV + 1) and d_col
+ * (nnz) are caller-owned device buffers sized from dgo_mesh_sizes; either
+ * may be NULL. Enqueued on the stream (device-to-device copies). */
 dgo_status dgo_mesh_csr(const dgo_mesh *mesh, int32_t *d_rowptr, int32_t *d_col,
                         dgo_stream stream);
 
@@ -142,7 +149,13 @@ dgo_status dgo_mesh_coo(const dgo_mesh *mesh, int32_t *d_row, int32_t *d_col, dg
  * vertices in local order. */
 dgo_status dgo_mesh_slots(const dgo_mesh *mesh, int32_t *d_slots, dgo_stream stream);
 
-/* Copy out the boundary-vertex mask: d_mask (nV bytes, 1 = boundary). */
+/* Copy out the boundary-vertex mask: the vertices of edges with one incident
+ * triangle, or of triangles with one incident tetrahedron. These are where
+ * the boundary conditions a geometric solver takes as input are imposed
+ * (Sec. 4, the programming model) and the kind of fixed-value set the quadratic-energy solve of the
+ * ARAP example takes (Sec. 4.2); dgo_pcg accepts such a mask. d_mask (nV
+ * bytes, 1 = boundary), caller-owned device memory. DGO_ERR_INVALID_ARG for
+ * NULL arguments; enqueued on the stream. */
 dgo_status dgo_mesh_boundary(const dgo_mesh *mesh, uint8_t *d_mask, dgo_stream stream);
 
 /* ----------------------------------------------------------------- assembly */
@@ -269,8 +282,16 @@ dgo_status dgo_spmv(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch, double
                     const void *d_Mdiag, double beta, const void *d_Kvals, int32_t k,
                     const void *d_x, void *d_y, dgo_stream stream);
 
+/* Options of dgo_pcg. The relative and absolute tolerances follow the
+ * paper's solver conventions (Sec. 6.2: absolute and relative tolerances, an
+ * iteration cap, a warning or, with strict, an error when the cap is reached
+ * with the tolerances unmet): a column stops as soon as
+ *   ||r||_2 <= max(rtol ||b_eff||_2, atol),
+ * r the recursive residual, b_eff the right-hand side after Dirichlet
+ * elimination. Every dot product is accumulated in FP64 in both dtypes (there
+ * is no option to turn that off). */
 typedef struct {
-    double rtol;          /* stop a column when ||r||_2 <= rtol ||b_eff||_2 */
+    double rtol;          /* relative tolerance (see above), >= 0 */
     int32_t max_iter;     /* iteration cap per column */
     int32_t fixed_iters;  /* != 0: run exactly max_iter iterations, no test */
     int32_t check_every;  /* host convergence poll period (iterations), >= 1 */
@@ -282,11 +303,13 @@ typedef struct {
     double rtol_initial;  /* > 0: a column also stops (and counts as
                              converged) when ||r||_2 <= rtol_initial ||r_0||_2,
                              r_0 the residual of the initial guess; 0: off */
+    double atol;          /* absolute tolerance on ||r||_2 (see above), >= 0;
+                             0: relative test only */
 } dgo_cg_opts;
 
 typedef struct {
     int32_t k;
-    int32_t converged_all;  /* 1 if every column met rtol */
+    int32_t converged_all;  /* 1 if every column met its tolerance */
     int32_t iters[64];      /* iterations per column */
     double relres[64];      /* recursive residual / ||b_eff|| per column */
     double true_relres[64]; /* ||b_eff - A u|| / ||b_eff|| evaluated in FP64 */

@@ -310,9 +310,10 @@ def spmv(mesh: Mesh, alpha, M, beta, K, x, out=None):
 
 def pcg(mesh: Mesh, alpha, M, beta, K, b, u0=None, mask=None, g=None, rtol=1e-8,
         max_iter=1000, fixed_iters=False, check_every=8, stall_iters=0, strict=False,
-        rtol_initial=0.0):
+        rtol_initial=0.0, atol=0.0):
     """Jacobi PCG on (alpha M + beta K) u = b; returns (u, report dict).
-    rtol_initial > 0 also stops a column at that fraction of its initial residual."""
+    A column stops at ||r|| <= max(rtol ||b||, atol); rtol_initial > 0 also
+    stops it at that fraction of its initial residual."""
     _need(M, "M")
     _need(K, "K", M.dtype)
     _need(b, "b", M.dtype)
@@ -322,7 +323,7 @@ def pcg(mesh: Mesh, alpha, M, beta, K, b, u0=None, mask=None, g=None, rtol=1e-8,
         _need(mask, "mask", torch.uint8)
         _need(g, "g", M.dtype, b.shape)
     opts = CgOpts(float(rtol), int(max_iter), int(bool(fixed_iters)), int(check_every),
-                  int(stall_iters), int(bool(strict)), float(rtol_initial))
+                  int(stall_iters), int(bool(strict)), float(rtol_initial), float(atol))
     rep = CgReport()
     check(lib().dgo_pcg(mesh.handle, _dtype_code(M.dtype), float(alpha), _ptr(M), float(beta),
                         _ptr(K), _ptr(mask), _ptr(g), k, _ptr(b), _ptr(u), C.byref(opts),

@@ -50,7 +50,7 @@ class EigReport(C.Structure):
 
 class CgOpts(C.Structure):
     _fields_ = [("rtol", f64), ("max_iter", i32), ("fixed_iters", i32), ("check_every", i32),
-                ("stall_iters", i32), ("strict", i32), ("rtol_initial", f64)]
+                ("stall_iters", i32), ("strict", i32), ("rtol_initial", f64), ("atol", f64)]
 
 
 class CgReport(C.Structure):

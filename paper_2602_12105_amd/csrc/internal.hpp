@@ -180,6 +180,10 @@ bool trace_active();
 // vertices, natural below).
 enum RowsMode { ROWS_NONE = 0, ROWS_NATURAL = 1, ROWS_AUTO = 2 };
 constexpr int32_t kRowOrderMinRows = 16384;
+// Most elements at one vertex that a mesh may have: every manifold mesh whose
+// vertices have at most 254 neighbours stays below it (a vertex of degree d
+// lies in at most d triangles, or 2 d - 4 tetrahedra).
+constexpr int32_t kMaxVertexElems = 1024;
 constexpr int32_t kEllMaxWidth = 16;
 // lds_budget: the LDS bytes one row block of the assembly may take (0: the
 // default, kRowBlockLdsBytes); rows per block are halved until it fits.

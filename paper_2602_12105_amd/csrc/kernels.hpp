@@ -24,7 +24,8 @@ struct CgCol {
 };
 
 struct CgParams {
-    double rtol, rtol0;  // stop at rtol ||b_eff|| or (rtol0 > 0) rtol0 ||r_0||
+    // stop at max(rtol ||b_eff||, atol) or (rtol0 > 0) at rtol0 ||r_0||
+    double rtol, rtol0, atol;
     int32_t max_iter, fixed, stall;
     int32_t k;
 };
@@ -804,7 +805,7 @@ __device__ inline void cg_stop_tests(CgCol &s, double rr, const CgParams &prm) {
     } else {
         s.since += 1;
     }
-    if (!prm.fixed && (sqrt(rr) <= prm.rtol * sqrt(s.bb) ||
+    if (!prm.fixed && (sqrt(rr) <= fmax(prm.rtol * sqrt(s.bb), prm.atol) ||
                        (prm.rtol0 > 0.0 && sqrt(rr) <= prm.rtol0 * sqrt(s.rr0)))) {
         s.converged = 1;
         s.active = 0;
@@ -836,7 +837,7 @@ __device__ inline void cg_sr_update(int mode, CgCol &s, const double *tot, const
         s.iters = 0;
         s.since = 0;
         s.stalled = 0;
-        const bool conv = !prm.fixed && sqrt(rr) <= prm.rtol * sqrt(s.bb);
+        const bool conv = !prm.fixed && sqrt(rr) <= fmax(prm.rtol * sqrt(s.bb), prm.atol);
         s.converged = conv ? 1 : 0;
         s.active = (!conv && prm.max_iter > 0) ? 1 : 0;
         s.rz = g;

@@ -389,7 +389,8 @@ class GpuExec {
 
     ~GpuExec() {
         if (graph_) (void)hipGraphExecDestroy(graph_);
-        for (auto &kv : prep_streams_) (void)hipStreamDestroy(kv.second);
+        for (auto &kv : prep_)
+            if (kv.second->stream) (void)hipStreamDestroy(kv.second->stream);
         if (cs_) (void)hipStreamDestroy(cs_);
         if (xs_) (void)hipStreamDestroy(xs_);
         if (h_desc_) (void)hipHostFree(h_desc_);
@@ -404,7 +405,16 @@ class GpuExec {
 
     dgo_status prepare(srv::Req &q) {
         (void)hipSetDevice(dev_);
-        hipStream_t ps = prep_stream();
+        PrepCtx *pc = prep_ctx();
+        if (!pc || !pc->stream) return DGO_ERR_DEVICE;
+        hipStream_t ps = pc->stream;
+        // every return drains the stream first: on a failure the scheduler
+        // releases the request's arena range and its caller may free its
+        // host buffers, so no copy or kernel of it may still be in flight
+        struct Drain {
+            hipStream_t s;
+            ~Drain() { (void)hipStreamSynchronize(s); }
+        } drain{ps};
         ReqDev *rd = new (std::nothrow) ReqDev();
         if (!rd) return DGO_ERR_NOMEM;
         q.exec = rd;
@@ -417,9 +427,17 @@ class GpuExec {
         R *dX = (R *)take(12 * nV);
         R *df = (R *)take(4 * nV * k);
         if (!dF || !dX || !df) return DGO_ERR_NOMEM;
-        DGO_HIP(hipMemcpyAsync(dF, in.h_F, 12 * in.nF, hipMemcpyHostToDevice, ps));
-        DGO_HIP(hipMemcpyAsync(dX, in.h_X, 12 * nV, hipMemcpyHostToDevice, ps));
-        DGO_HIP(hipMemcpyAsync(df, in.h_f, 4 * nV * k, hipMemcpyHostToDevice, ps));
+        // the inputs go through this thread's pinned staging buffer (the
+        // caller's arrays are pageable)
+        const size_t bF = 12 * (size_t)in.nF, bX = 12 * (size_t)nV, bf = 4 * (size_t)(nV * k);
+        char *stage = (char *)pc->staging(bF + bX + bf);
+        if (!stage) return DGO_ERR_NOMEM;
+        memcpy(stage, in.h_F, bF);
+        memcpy(stage + bF, in.h_X, bX);
+        memcpy(stage + bF + bX, in.h_f, bf);
+        DGO_HIP(hipMemcpyAsync(dF, stage, bF, hipMemcpyHostToDevice, ps));
+        DGO_HIP(hipMemcpyAsync(dX, stage + bF, bX, hipMemcpyHostToDevice, ps));
+        DGO_HIP(hipMemcpyAsync(df, stage + bF + bX, bf, hipMemcpyHostToDevice, ps));
         dgo_allocator al{bump_alloc, bump_free, &rd->bump};
         // the batched kernels read the CSR directly; the one-at-a-time
         // baseline goes through the SpMV entry points, which need row
@@ -520,9 +538,12 @@ class GpuExec {
     dgo_status finish(srv::Req &q) {
         ReqDev *rd = (ReqDev *)q.exec;
         (void)hipSetDevice(dev_);
-        DGO_HIP(hipMemcpyAsync(q.in.h_u, rd->desc.u, 4 * (size_t)q.in.nV * q.in.k,
-                               hipMemcpyDeviceToHost, xs_));
+        const size_t bytes = 4 * (size_t)q.in.nV * q.in.k;
+        void *stage = res_stage_.staging(bytes);  // pinned; the caller's h_u is pageable
+        if (!stage) return DGO_ERR_NOMEM;
+        DGO_HIP(hipMemcpyAsync(stage, rd->desc.u, bytes, hipMemcpyDeviceToHost, xs_));
         DGO_HIP(hipStreamSynchronize(xs_));
+        memcpy(q.in.h_u, stage, bytes);
         return DGO_OK;
     }
 
@@ -536,15 +557,48 @@ class GpuExec {
     }
 
   private:
-    hipStream_t prep_stream() {
+    // Pinned host staging, grown on demand (one per preparation thread and
+    // one for the completion thread; each is used by one thread only).
+    struct Staging {
+        void *p = nullptr;
+        size_t cap = 0;
+        void *staging(size_t bytes) {
+            if (bytes <= cap) return p;
+            if (p) (void)hipHostFree(p);
+            p = nullptr;
+            cap = 0;
+            const size_t want = bytes + bytes / 4;
+            if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+                return nullptr;
+            }
+            cap = want;
+            return p;
+        }
+        ~Staging() {
+            if (p) (void)hipHostFree(p);
+        }
+    };
+    struct PrepCtx : Staging {
+        hipStream_t stream = nullptr;
+    };
+
+    // The calling preparation thread's stream and staging buffer (created on
+    // its first request; NULL if the stream cannot be created).
+    PrepCtx *prep_ctx() {
         std::lock_guard<std::mutex> lk(mu_);
         auto id = std::this_thread::get_id();
-        auto it = prep_streams_.find(id);
-        if (it != prep_streams_.end()) return it->second;
-        hipStream_t s = nullptr;
-        (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-        prep_streams_[id] = s;
-        return s;
+        auto it = prep_.find(id);
+        if (it != prep_.end()) return it->second.get();
+        auto pc = std::make_unique<PrepCtx>();
+        if (hipStreamCreateWithFlags(&pc->stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        PrepCtx *r = pc.get();
+        prep_[id] = std::move(pc);
+        return r;
     }
 
     void launch_tick(int32_t chunk) {
@@ -554,6 +608,7 @@ class GpuExec {
         CgParams prm;
         prm.rtol = 0.0;
         prm.rtol0 = 0.0;
+        prm.atol = 0.0;
         prm.max_iter = o_.cg_iters;
         prm.fixed = 1;
         prm.stall = 0;
@@ -601,7 +656,8 @@ class GpuExec {
     hipGraphExec_t graph_ = nullptr;
     int32_t graph_chunk_ = -1;
     std::mutex mu_;
-    std::unordered_map<std::thread::id, hipStream_t> prep_streams_;
+    std::unordered_map<std::thread::id, std::unique_ptr<PrepCtx>> prep_;
+    Staging res_stage_;  // result copies (completion thread)
 };
 
 }  // namespace

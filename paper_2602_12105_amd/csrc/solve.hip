@@ -1077,6 +1077,7 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     CgParams prm;
     prm.rtol = o.rtol;
     prm.rtol0 = o.rtol_initial;
+    prm.atol = o.atol;
     prm.max_iter = o.max_iter;
     prm.fixed = o.fixed_iters;
     prm.stall = o.stall_iters;
@@ -1184,7 +1185,7 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
             const CgCol &q = sc[c];
             if (!q.active) continue;
             any = true;
-            double target = o.rtol * o.rtol * q.bb;
+            double target = std::max(o.rtol * o.rtol * q.bb, o.atol * o.atol);
             if (o.rtol_initial > 0.0) target = std::max(target, o.rtol_initial * o.rtol_initial * q.rr0);
             if (last_it[c] >= 0 && q.iters > last_it[c] && q.rr > 0.0 && q.rr < last_rr[c] && target > 0.0) {
                 // log of the residual norm^2 ratio per iteration (< 0)
@@ -1248,9 +1249,9 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
         }
     }
     if (!all && !o.fixed_iters) {
-        if (o.strict) return fail(DGO_ERR_NOT_CONVERGED, "dgo_pcg: a column did not reach rtol");
+        if (o.strict) return fail(DGO_ERR_NOT_CONVERGED, "dgo_pcg: a column did not reach its tolerance");
         if (getenv("DGO_LOG") && atoi(getenv("DGO_LOG")) > 0)
-            fprintf(stderr, "dgo_pcg: warning: not every column reached rtol\n");
+            fprintf(stderr, "dgo_pcg: warning: not every column reached its tolerance\n");
     }
     return DGO_OK;
 }
@@ -1321,8 +1322,9 @@ extern "C" dgo_status dgo_pcg(const dgo_mesh *m, dgo_dtype dtype, double alpha, 
         o.stall_iters = 0;
         o.strict = 0;
         o.rtol_initial = 0.0;
+        o.atol = 0.0;
     }
-    if (o.max_iter < 0 || !(o.rtol >= 0.0) || !(o.rtol_initial >= 0.0))
+    if (o.max_iter < 0 || !(o.rtol >= 0.0) || !(o.rtol_initial >= 0.0) || !(o.atol >= 0.0))
         return fail(DGO_ERR_INVALID_ARG, "dgo_pcg: bad options");
     hipStream_t s = (hipStream_t)stream;
     if (dtype == DGO_F64)

@@ -188,6 +188,12 @@ __global__ void k_max_row(const int32_t *rowptr, int32_t nV, int32_t *mx) {
     atomicMax(mx, rowptr[v + 1] - rowptr[v]);
 }
 
+__global__ void k_max_count(const int32_t *cnt, int32_t nV, int32_t *mx) {
+    int32_t v = blockIdx.x * T + threadIdx.x;
+    if (v >= nV) return;
+    atomicMax(mx, cnt[v]);
+}
+
 __global__ void k_inc_count(const int32_t *elem, int64_t n_inc, int32_t *cnt) {
     int64_t o = (int64_t)blockIdx.x * T + threadIdx.x;
     if (o >= n_inc) return;
@@ -328,6 +334,29 @@ __global__ void k_block_nnz(const int32_t *rowptr, const int32_t *vtptr, int32_t
     atomicMax(&mx[1], vtptr[r1] - vtptr[r0]);
 }
 
+// Pinned host memory for the small device-to-host readbacks of a topology
+// build (status flags, the edge count): one buffer per host thread, so that
+// concurrent builds (the server's preparation threads) never copy into
+// pageable stack memory.
+struct PinnedWords {
+    int32_t *p = nullptr;
+    ~PinnedWords() {
+        if (p) (void)hipHostFree(p);
+    }
+    int32_t *get() {
+        if (!p && hipHostMalloc((void **)&p, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        return p;
+    }
+};
+
+int32_t *readback_words() {
+    static thread_local PinnedWords w;
+    return w.get();
+}
+
 struct Tmp {
     const Alloc &al;
     hipStream_t s;
@@ -359,30 +388,40 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
     if (!m->elem) return fail(DGO_ERR_NOMEM, "mesh: element copy allocation failed");
     if (ninc) DGO_HIP(hipMemcpyAsync(m->elem, d_elem, sizeof(int32_t) * ninc, hipMemcpyDeviceToDevice, s));
 
-    // a1: validation
+    // a1: validation, and the most elements at one vertex (the per-vertex
+    // sorts below are quadratic in it: a vertex past the supported degree is
+    // rejected before they run)
+    int32_t *hf = readback_words();
+    if (!hf) return fail(DGO_ERR_NOMEM, "mesh: pinned readback allocation failed");
     int32_t *flags = tmp.get<int32_t>(8);
-    int32_t *hflags = nullptr;
-    if (!flags) return fail(DGO_ERR_NOMEM, "mesh: allocation failed");
+    int32_t *ecnt = tmp.get<int32_t>(nV + 1);
+    if (!flags || !ecnt) return fail(DGO_ERR_NOMEM, "mesh: allocation failed");
     DGO_HIP(hipMemsetAsync(flags, 0, 8 * sizeof(int32_t), s));
+    DGO_HIP(hipMemsetAsync(ecnt, 0, sizeof(int32_t) * (nV + 1), s));
     if (ne) k_validate<<<grid_for(ne, T), T, 0, s>>>(m->elem, ne, nv, nV, flags);
     DGO_HIP(hipGetLastError());
-    int32_t hf[8];
-    DGO_HIP(hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s));
+    DGO_HIP(hipMemcpyAsync(hf, flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DGO_HIP(hipStreamSynchronize(s));
-    (void)hflags;
     if (hf[0]) return fail(DGO_ERR_INDEX_RANGE, "mesh: element index outside [0, nV)");
     if (hf[1]) return fail(DGO_ERR_INVALID_ARG, "mesh: repeated vertex within an element");
+    if (ninc) k_inc_count<<<grid_for(ninc, T), T, 0, s>>>(m->elem, ninc, ecnt);
+    if (nV) k_max_count<<<grid_for(nV, T), T, 0, s>>>(ecnt, nV, flags + 7);
+    DGO_HIP(hipGetLastError());
+    DGO_HIP(hipMemcpyAsync(hf + 7, flags + 7, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DGO_HIP(hipStreamSynchronize(s));
+    if (hf[7] > kMaxVertexElems)
+        return fail(DGO_ERR_UNSUPPORTED, "mesh: a vertex lies in more than " +
+                                             std::to_string(kMaxVertexElems) + " elements");
 
     // a2: edges by owner-vertex bucketing
     const size_t stmp = scan_tmp_elems((int64_t)nV + 1);
     int32_t *cnt = tmp.get<int32_t>(nV + 1);
     int32_t *boff = tmp.get<int32_t>(nV + 1);
     int32_t *cursor = tmp.get<int32_t>(nV + 1);
-    int32_t *ecnt = tmp.get<int32_t>(nV + 1);
     int32_t *lcnt = tmp.get<int32_t>(nV + 1);
     int32_t *stmpb = tmp.get<int32_t>((int64_t)stmp + 1);
     uint64_t *bucket = tmp.get<uint64_t>(nkeys);
-    if (!cnt || !boff || !cursor || !ecnt || !lcnt || !stmpb || !bucket)
+    if (!cnt || !boff || !cursor || !lcnt || !stmpb || !bucket)
         return fail(DGO_ERR_NOMEM, "mesh: topology scratch allocation failed");
     DGO_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (nV + 1), s));
     DGO_HIP(hipMemsetAsync(cursor, 0, sizeof(int32_t) * (nV + 1), s));
@@ -398,10 +437,9 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
     DGO_HIP(hipGetLastError());
     int32_t *eoff = cnt;  // reuse
     DGO_TRY(exclusive_scan(ecnt, eoff, nV, stmpb, s));
-    int32_t nE32 = 0;
-    DGO_HIP(hipMemcpyAsync(&nE32, eoff + nV, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DGO_HIP(hipMemcpyAsync(hf + 8, eoff + nV, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DGO_HIP(hipStreamSynchronize(s));
-    m->nE = nE32;
+    m->nE = hf[8];
     m->nnz = (int64_t)nV + 2 * m->nE;
     if (m->nnz > INT32_MAX) return fail(DGO_ERR_UNSUPPORTED, "mesh: more than 2^31 CSR entries");
 
@@ -490,7 +528,7 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
         int32_t nb = (int32_t)((nV + rpb - 1) / rpb);
         if (nb) k_block_nnz<<<grid_for(nb, T), T, 0, s>>>(m->rowptr, m->vtptr, nV, rpb, flags + 5);
         DGO_HIP(hipGetLastError());
-        DGO_HIP(hipMemcpyAsync(hf, flags, sizeof hf, hipMemcpyDeviceToHost, s));
+        DGO_HIP(hipMemcpyAsync(hf, flags, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         DGO_HIP(hipStreamSynchronize(s));
         if (assembly_lds_bytes(dim, 8, rpb, hf[5], hf[6]) <= budget || rpb <= 1) break;
         rpb /= 2;
@@ -559,33 +597,51 @@ static dgo_status build_row_desc(dgo_mesh *m, hipStream_t s, bool bfs) {
     m->rdesc = (int2 *)m->alloc.get(sizeof(int2) * (size_t)nV, s);
     m->rlen = (uint8_t *)m->alloc.get((size_t)nV, s);
     if (!m->rdesc || !m->rlen) return fail(DGO_ERR_NOMEM, "mesh: row descriptor allocation failed");
-    std::vector<int32_t> order;
+    // Host staging of the breadth-first order: pinned memory (rowptr, col and
+    // the order), released only after the stream has drained, on every return
+    // path, so no copy in flight ever touches freed host memory.
+    struct Staging {
+        hipStream_t s;
+        int32_t *h = nullptr;
+        ~Staging() {
+            if (h) {
+                (void)hipStreamSynchronize(s);
+                (void)hipHostFree(h);
+            }
+        }
+    } stg{s};
     if (bfs && nV >= kRowOrderMinRows) {
-        std::vector<int32_t> rp((size_t)nV + 1), cl((size_t)m->nnz);
-        DGO_HIP(hipMemcpyAsync(rp.data(), m->rowptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost, s));
-        DGO_HIP(hipMemcpyAsync(cl.data(), m->col, sizeof(int32_t) * cl.size(), hipMemcpyDeviceToHost, s));
+        const size_t words = ((size_t)nV + 1) + (size_t)m->nnz + (size_t)nV;
+        if (hipHostMalloc((void **)&stg.h, sizeof(int32_t) * words, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            stg.h = nullptr;
+            return fail(DGO_ERR_NOMEM, "mesh: pinned staging allocation failed");
+        }
+        int32_t *rp = stg.h, *cl = rp + nV + 1, *order = cl + m->nnz;
+        DGO_HIP(hipMemcpyAsync(rp, m->rowptr, sizeof(int32_t) * ((size_t)nV + 1), hipMemcpyDeviceToHost, s));
+        DGO_HIP(hipMemcpyAsync(cl, m->col, sizeof(int32_t) * (size_t)m->nnz, hipMemcpyDeviceToHost, s));
         DGO_HIP(hipStreamSynchronize(s));
-        order.reserve((size_t)nV);
         std::vector<uint8_t> seen((size_t)nV, 0);
+        int64_t tail = 0;
         for (int32_t root = 0; root < nV; ++root) {
             if (seen[root]) continue;
             seen[root] = 1;
-            size_t head = order.size();
-            order.push_back(root);
-            while (head < order.size()) {
+            int64_t head = tail;
+            order[tail++] = root;
+            while (head < tail) {
                 const int32_t v = order[head++];
                 for (int32_t t = rp[v]; t < rp[v + 1]; ++t) {
                     const int32_t j = cl[t];
                     if (!seen[j]) {
                         seen[j] = 1;
-                        order.push_back(j);
+                        order[tail++] = j;
                     }
                 }
             }
         }
         m->order = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)nV, s);
         if (!m->order) return fail(DGO_ERR_NOMEM, "mesh: row order allocation failed");
-        DGO_HIP(hipMemcpyAsync(m->order, order.data(), sizeof(int32_t) * (size_t)nV,
+        DGO_HIP(hipMemcpyAsync(m->order, order, sizeof(int32_t) * (size_t)nV,
                                hipMemcpyHostToDevice, s));
     }
     k_row_desc<<<grid_for(nV, T), T, 0, s>>>(m->order, m->rowptr, nV, m->rdesc, m->rlen);
@@ -608,7 +664,7 @@ static dgo_status build_row_desc(dgo_mesh *m, hipStream_t s, bool bfs) {
         DGO_HIP(hipGetLastError());
         m->ell_w = W;
     }
-    DGO_HIP(hipStreamSynchronize(s));  // `order` is freed on return
+    DGO_HIP(hipStreamSynchronize(s));
     return DGO_OK;
 }
 

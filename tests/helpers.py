@@ -32,6 +32,22 @@ def assert_vec_close(got, ref, rtol, scale=None, what="v"):
     assert np.size(bad) == 0, f"{what}: max err {err.max()} vs scale {np.max(s)}"
 
 
+def assert_cols_close(got, ref, rtol, what="u"):
+    """Element by element, |got_ic - ref_ic| <= rtol * max_i |ref_ic|: every
+    column of a solution block is an independent system, scaled by its own
+    largest entry (the vector form of the row-scaled metric)."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    n = ref.shape[0]
+    got, ref = got.reshape(n, -1), ref.reshape(n, -1)
+    sc = np.abs(ref).max(axis=0)
+    err = np.abs(got - ref)
+    bad = ~(err <= rtol * sc[None, :])
+    worst = float((err / np.where(sc > 0, sc, 1.0)[None, :]).max()) if err.size else 0.0
+    assert not bad.any(), f"{what}: {int(bad.sum())} entries off; worst scaled error {worst:.3e} > {rtol}"
+    return worst
+
+
 def spmv_scale(rowptr, col, alpha, M, beta, K, x):
     """sum_j |A_ij| |x_j| per row and column, the SpMV error scale."""
     rowptr, col = np.asarray(rowptr), np.asarray(col)

@@ -12,10 +12,11 @@ import torch
 
 import meshgen
 import oracle
+from helpers import RTOL
 
 pytestmark = pytest.mark.gpu
 
-dgo = pytest.importorskip("paper_2602_12105_amd")
+import paper_2602_12105_amd as dgo  # noqa: E402  (no skip: a broken import fails the suite)
 DEV = "cuda:0"
 
 
@@ -46,27 +47,73 @@ def _check_pairs(m, K, M, lam, U, tol):
     return rn, np.abs(G - np.eye(Uh.shape[1])).max()
 
 
+def _pair_errors(m, K, M, lam, U, lam_all, U_all):
+    """Error bounds of computed pairs (lam_j, u_j) of K u = lam M u from their
+    residuals, evaluated in FP64 on the host from the library's K and M, and
+    the errors themselves against the oracle's pairs (lam_all, U_all). With
+    r_j = K u_j - lam_j M u_j and ||u_j||_M = 1 some eigenvalue lies within
+    rho_j = ||r_j||_{M^-1} of lam_j; the eigenvalues within 10 rho_j of lam_j
+    form the pair's cluster C_j (one eigenvalue when it is well separated),
+    and the M-angle between u_j and the span of C_j's eigenvectors is at most
+    rho_j / gap_j (Davis-Kahan), gap_j the distance from lam_j to the
+    eigenvalues outside C_j. Returns rho, the max-norm distance of each u_j
+    from its M-projection onto that span, and the bound
+    sqrt(2) sin(theta) / sqrt(min M) of that distance."""
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    Kh, Mh = K.double().cpu().numpy(), M.double().cpu().numpy()
+    A = sp.csr_matrix((Kh, col, rp))
+    Uh, lh = U.double().cpu().numpy(), lam.numpy()
+    Uh = Uh / np.sqrt((Mh[:, None] * Uh * Uh).sum(0))[None, :]
+    R = A @ Uh - (Mh[:, None] * Uh) * lh[None, :]
+    rn = np.sqrt(((R ** 2) / Mh[:, None]).sum(axis=0))
+    err, bnd = [], []
+    for j, l in enumerate(lh):
+        inside = np.abs(lam_all - l) <= 10.0 * rn[j]
+        if not inside.any():
+            inside[int(np.argmin(np.abs(lam_all - l)))] = True
+        gap = np.min(np.abs(lam_all[~inside] - l))
+        Q = U_all[:, inside]
+        proj = Q @ (Q.T @ (Mh * Uh[:, j]))
+        err.append(np.abs(Uh[:, j] - proj).max())
+        bnd.append(np.sqrt(2.0) * min(1.0, rn[j] / gap) / np.sqrt(Mh.min()))
+    return rn, np.array(err), np.array(bnd)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_grid_against_oracle(dtype):
+    """Eigenpairs of a jittered grid against the oracle's dense solution of the
+    same (in FP32: FP32-rounded) K and M. Eigenvalues meet the stated bar
+    (1e-12 / 1e-5 of max(|lam|, |sigma|)); eigenvectors, which the solver's
+    residual tolerance determines only up to residual / gap, are compared
+    element by element within the a-posteriori bound of each computed pair
+    (and the pair's residual meets the requested tolerance)."""
     print(f"[eigs] grid 30 {dtype}", flush=True)
     X, F = meshgen.grid2d(30, 0.2, 5)
     td = torch.float64 if dtype == "f64" else torch.float32
     m, K, M = _assembled(X, F, td)
     k = 6
     # FP32 vectors bound the attainable residual near eps_32 * lambda_max / lambda
-    lam, U, rep = dgo.eigs_smallest(m, M, K, k, tol=1e-10 if dtype == "f64" else 2e-3)
+    tol = 1e-11 if dtype == "f64" else 2e-3
+    lam, U, rep = dgo.eigs_smallest(m, M, K, k, tol=tol)
     print(rep, flush=True)
     assert rep["converged"], rep
     rp, col = [t.cpu().numpy() for t in m.csr()]
-    lo, Uo = oracle.eigs_smallest(rp, col, K.double().cpu().numpy(), M.double().cpu().numpy(), k)
-    if dtype == "f64":
-        np.testing.assert_allclose(lam.numpy(), lo, rtol=1e-10, atol=1e-10)
-        np.testing.assert_allclose(U.cpu().numpy(), Uo, atol=1e-7)
-        rn, orth = _check_pairs(m, K, M, lam, U, 1e-10)
-        assert orth <= 1e-12
-    else:
-        np.testing.assert_allclose(lam.numpy(), lo, rtol=1e-4, atol=1e-4)
-        np.testing.assert_allclose(U.double().cpu().numpy(), Uo, atol=2e-3 * np.abs(Uo).max())
+    Kh, Mh = K.double().cpu().numpy(), M.double().cpu().numpy()
+    lall, Uall = oracle.eigs_smallest(rp, col, Kh, Mh, k + 4)
+    lo = lall[:k]
+    scale = np.maximum(np.abs(lo), abs(rep["sigma"]))
+    el = np.abs(lam.numpy() - lo) / scale
+    rn, ev, vb = _pair_errors(m, K, M, lam, U, lall, Uall)
+    print(f"  eigenvalue errors {el}, residuals {rn}, vector errors {ev}, bounds {vb}", flush=True)
+    assert np.all(el <= RTOL[dtype]), el
+    assert np.all(rn <= tol * scale * 1.01), rn
+    assert np.all(ev <= vb), (ev, vb)
+    # well-separated pairs also equal the oracle's canonically signed vector
+    for j in range(k):
+        if vb[j] < 1e-2:
+            assert np.abs(U.double().cpu().numpy()[:, j] - Uall[:, j]).max() <= vb[j]
+    rn2, orth = _check_pairs(m, K, M, lam, U, tol)
+    assert orth <= (1e-12 if dtype == "f64" else 1e-5)
 
 
 def test_flat_torus_closed_form():

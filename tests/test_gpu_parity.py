@@ -12,11 +12,11 @@ import torch
 
 import meshgen
 import oracle
-from helpers import MESHES, RTOL, assert_csr_close, spmv_scale
+from helpers import MESHES, RTOL, assert_cols_close, assert_csr_close, spmv_scale
 
 pytestmark = pytest.mark.gpu
 
-dgo = pytest.importorskip("paper_2602_12105_amd")
+import paper_2602_12105_amd as dgo  # noqa: E402  (no skip: a broken import fails the suite)
 DEV = "cuda:0"
 
 
@@ -71,6 +71,13 @@ def test_mesh_errors():
     with pytest.raises(dgo.DgoError) as e:
         dgo.Mesh(F, n + 1)
     assert e.value.status == "UNSUPPORTED"
+    # a vertex in more elements than any supported degree allows is rejected
+    # before the per-vertex sorts run (their cost is quadratic in that count)
+    n = 5000
+    F = torch.tensor([[0, i, i + 1] for i in range(1, n)], dtype=torch.int32, device=DEV)
+    with pytest.raises(dgo.DgoError) as e:
+        dgo.Mesh(F, n + 1)
+    assert e.value.status == "UNSUPPORTED" and "elements" in str(e.value)
 
 
 def _assemble_check(name, dtype, batch=1, clamp=None):
@@ -234,11 +241,28 @@ def _cfg2_system(level, k, dtype, seed=1):
     return m, K, M, b
 
 
+def _oracle_same_iters(rp, col, alpha, Mh, beta, Kh, bh, iters, mask=None, g=None):
+    """The oracle's PCG run column by column for exactly the iteration count
+    the GPU reported for that column: the same iterate on both sides, so a
+    converged solve is compared at the element-wise bar, not at the solver
+    tolerance."""
+    bh = bh.reshape(bh.shape[0], -1)
+    out = np.empty_like(bh)
+    for c in range(bh.shape[1]):
+        gc = None if g is None else np.ascontiguousarray(g.reshape(bh.shape[0], -1)[:, c])
+        uo, its, _ = oracle.pcg(rp, col, alpha, Mh, beta, Kh, np.ascontiguousarray(bh[:, c]),
+                                mask=mask, g=gc, rtol=0.0, max_iter=int(iters[c]))
+        assert int(its[0]) == int(iters[c])
+        out[:, c] = uo
+    return out
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("iters", [1, 30, 31])
+@pytest.mark.parametrize("iters", [1, 30, 31, 60])
 def test_pcg_fixed_iterations_match_oracle(dtype, iters):
-    """The same iteration count on both sides: iterates agree element by element
-    (odd and even counts: x takes the steps in pairs)."""
+    """The same iteration count on both sides: iterates agree element by
+    element at the stated bar (odd and even counts: x takes the steps in
+    pairs)."""
     print(f"[pcg-fixed] {dtype} {iters}", flush=True)
     m, K, M, b = _cfg2_system(5, 8, dtype)
     u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=iters, fixed_iters=True)
@@ -247,9 +271,8 @@ def test_pcg_fixed_iterations_match_oracle(dtype, iters):
     uo, its, rr = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3,
                              K.double().cpu().numpy(), b.double().cpu().numpy(), rtol=0.0,
                              max_iter=iters)
-    tol = 1e-10 if dtype == "f64" else 1e-4
-    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
-    assert err <= tol, err
+    w = assert_cols_close(u.double().cpu().numpy(), uo, RTOL[dtype])
+    print(f"  worst column-scaled error {w:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -265,9 +288,7 @@ def test_pcg_k13_match_oracle(dtype, k):
     rp, col = [t.cpu().numpy() for t in m.csr()]
     uo, _, _ = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3, K.double().cpu().numpy(),
                           b.double().cpu().numpy(), rtol=0.0, max_iter=25)
-    tol = 1e-10 if dtype == "f64" else 1e-4
-    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
-    assert err <= tol, err
+    assert_cols_close(u.double().cpu().numpy(), uo, RTOL[dtype])
     assert max(rep["true_relres"]) < 1.0
 
 
@@ -288,42 +309,47 @@ def test_pcg_long_rows_match_oracle(name, dtype):
     rp, col = [t.cpu().numpy() for t in m.csr()]
     uo, _, _ = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3, K.double().cpu().numpy(),
                           b.double().cpu().numpy(), rtol=0.0, max_iter=30)
-    tol = 1e-10 if dtype == "f64" else 1e-4
-    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
-    assert err <= tol, err
+    assert_cols_close(u.double().cpu().numpy(), uo, RTOL[dtype])
 
 
 def test_pcg_converges_cfg2_f64():
+    """Config 2 at full size (icosphere L7, 8 right-hand sides, rtol 1e-8):
+    every column stops within one iteration of the oracle's own stop, and
+    the solution equals the oracle's iterate of the same count at 1e-12."""
     print("[pcg] icosphere L7 k=8 f64", flush=True)
     m, K, M, b = _cfg2_system(7, 8, "f64")
     u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-8, max_iter=500)
     assert rep["converged_all"], rep
     assert max(rep["true_relres"]) <= 2e-8
     rp, col = [t.cpu().numpy() for t in m.csr()]
-    uo, its, rr = oracle.pcg(rp, col, 1.0, M.cpu().numpy(), 1e-3, K.cpu().numpy(),
-                             b.cpu().numpy(), rtol=1e-8, max_iter=500)
+    Kh, Mh, bh = K.cpu().numpy(), M.cpu().numpy(), b.cpu().numpy()
+    uo, its, rr = oracle.pcg(rp, col, 1.0, Mh, 1e-3, Kh, bh, rtol=1e-8, max_iter=500)
     assert all(abs(a - o) <= 1 for a, o in zip(rep["iters"], its)), (rep["iters"], its)
-    err = np.abs(u.cpu().numpy() - uo).max() / np.abs(uo).max()
-    assert err <= 1e-6, err
+    ref = _oracle_same_iters(rp, col, 1.0, Mh, 1e-3, Kh, bh, rep["iters"])
+    w = assert_cols_close(u.cpu().numpy(), ref, RTOL["f64"])
+    print(f"  worst column-scaled error {w:.2e}", flush=True)
 
 
-def test_pcg_cfg2_f32_accuracy():
-    """FP32 storage, FP64 dots: solution within 1e-5 of the tight FP64 solution."""
-    print("[pcg] icosphere L6 k=8 f32", flush=True)
-    m64, K64, M64, b64 = _cfg2_system(6, 8, "f64")
-    m, K, M, b = _cfg2_system(6, 8, "f32")
+@pytest.mark.parametrize("level", [6, 7])
+def test_pcg_cfg2_f32_accuracy(level):
+    """FP32 storage and SpMV, FP64 dots, stagnation stop: the solution is
+    within 1e-5 (element by element, column-scaled) of the oracle's tight
+    FP64 solution of the same FP32-rounded system; level 7 is config 2's
+    full size."""
+    print(f"[pcg] icosphere L{level} k=8 f32", flush=True)
+    m, K, M, b = _cfg2_system(level, 8, "f32")
     u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-8, max_iter=1000, stall_iters=20)
     rp, col = [t.cpu().numpy() for t in m.csr()]
     uo, _, _ = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3, K.double().cpu().numpy(),
                           b.double().cpu().numpy(), rtol=1e-14, max_iter=5000)
-    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
-    assert err <= 1e-5, (err, rep)
+    w = assert_cols_close(u.double().cpu().numpy(), uo, RTOL["f32"])
+    print(f"  worst column-scaled error {w:.2e}; iterations {rep['iters']}", flush=True)
 
 
-@pytest.mark.parametrize("n,dtype", [(17, "f64"), (17, "f32"), (26, "f64")])
-def test_pcg_dirichlet_cube(n, dtype):
-    """n = 26 (17,576 vertices) runs the masked SpMV in breadth-first row order."""
-    print(f"[pcg-dirichlet] cube{n} {dtype}", flush=True)
+def _cube_problem(n, dtype):
+    """Config 3's Dirichlet Poisson problem (manufactured solution
+    sin(pi x) sin(pi y) sin(pi z), its values on the boundary, source
+    3 pi^2 u*, b = M f) on the jittered Kuhn cube with n^3 vertices."""
     X, T = meshgen.cube_tets(n, 0.15, 0)
     m = dgo.Mesh(torch.from_numpy(T).to(DEV), X.shape[0])
     td = torch.float64 if dtype == "f64" else torch.float32
@@ -332,17 +358,89 @@ def test_pcg_dirichlet_cube(n, dtype):
     us = np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
     g = torch.from_numpy(us).to(DEV, td)
     b = (M * torch.from_numpy(3 * np.pi ** 2 * us).to(DEV, td)).contiguous()
-    rtol = 1e-10 if dtype == "f64" else 1e-6
-    u, rep = dgo.pcg(m, 0.0, M, 1.0, K, b, mask=mask, g=g, rtol=rtol, max_iter=3000,
-                     stall_iters=30 if dtype == "f32" else 0)
+    return m, K, M, mask, g, b
+
+
+@pytest.mark.parametrize("n", [17, 26, 64])
+def test_pcg_dirichlet_cube_f64(n):
+    """Config 3 in FP64 (n = 64 is its full size, 262,144 vertices; n = 26
+    runs the masked SpMV in breadth-first row order): the solve to rtol 1e-8
+    equals the oracle's iterate of the same count at 1e-12, and the solve to
+    1e-14 equals the oracle's tight solution at 1e-12."""
+    print(f"[pcg-dirichlet] cube{n} f64", flush=True)
+    m, K, M, mask, g, b = _cube_problem(n, "f64")
     rp, col = [t.cpu().numpy() for t in m.csr()]
-    uo, its, _ = oracle.pcg(rp, col, 0.0, M.double().cpu().numpy(), 1.0, K.double().cpu().numpy(),
-                            b.double().cpu().numpy(), mask=mask.cpu().numpy(),
-                            g=g.double().cpu().numpy(), rtol=1e-14, max_iter=5000)
-    err = np.abs(u.double().cpu().numpy() - uo).max() / np.abs(uo).max()
-    assert err <= (1e-8 if dtype == "f64" else 2e-4), (err, rep)
-    bm = mask.cpu().numpy() == 1
-    assert np.array_equal(u.double().cpu().numpy()[bm], g.double().cpu().numpy()[bm])
+    Kh, Mh, bh, gh, mh = (t.cpu().numpy() for t in (K, M, b, g, mask))
+    u, rep = dgo.pcg(m, 0.0, M, 1.0, K, b, mask=mask, g=g, rtol=1e-8, max_iter=5000)
+    assert rep["converged_all"], rep
+    ref = _oracle_same_iters(rp, col, 0.0, Mh, 1.0, Kh, bh, rep["iters"], mask=mh, g=gh)
+    w = assert_cols_close(u.cpu().numpy(), ref, RTOL["f64"])
+    bm = mh == 1
+    assert np.array_equal(u.cpu().numpy()[bm], gh[bm])
+    ut, rep_t = dgo.pcg(m, 0.0, M, 1.0, K, b, mask=mask, g=g, rtol=1e-14, max_iter=5000,
+                        stall_iters=30)
+    uo, its, _ = oracle.pcg(rp, col, 0.0, Mh, 1.0, Kh, bh, mask=mh, g=gh, rtol=1e-14,
+                            max_iter=20000)
+    wt = assert_cols_close(ut.cpu().numpy(), uo, RTOL["f64"])
+    print(f"  same-count error {w:.2e}, tight error {wt:.2e}, iterations {rep['iters']}",
+          flush=True)
+
+
+def _jacobi_condition(rp, col, alpha, Mh, beta, Kh, mask=None, steps=400, seed=3):
+    """2-norm condition number of the Jacobi-scaled operator D^-1/2 A D^-1/2
+    (A restricted to the unmasked rows and columns), estimated from the
+    extreme Ritz values of a plain Lanczos run on the oracle-side matrices."""
+    n = rp.size - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    A = sp.csr_matrix((beta * Kh, col, rp), shape=(n, n)) + sp.diags(alpha * Mh)
+    keep = np.ones(n, bool) if mask is None else (mask == 0)
+    A = A[keep][:, keep].tocsr()
+    d = 1.0 / np.sqrt(A.diagonal())
+    S = sp.diags(d) @ A @ sp.diags(d)
+    q = meshgen.normal(seed, S.shape[0])
+    q /= np.linalg.norm(q)
+    qp = np.zeros_like(q)
+    al, be = [], []
+    bprev = 0.0
+    for _ in range(steps):
+        w = S @ q - bprev * qp
+        a = float(q @ w)
+        w -= a * q
+        bn = float(np.linalg.norm(w))
+        al.append(a)
+        be.append(bn)
+        if bn == 0.0:
+            break
+        qp, q, bprev = q, w / bn, bn
+    T = np.diag(al) + np.diag(be[:-1], 1) + np.diag(be[:-1], -1)
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[-1] / ev[0])
+
+
+@pytest.mark.parametrize("n", [17, 64])
+def test_pcg_dirichlet_cube_f32_attainable(n):
+    """Config 3 in FP32 (n = 64: its full size). FP32 vectors and SpMV cannot
+    reach 1e-5 here in general: the attainable relative accuracy of CG in a
+    working precision u is of order kappa u, kappa the condition number of
+    the Jacobi-scaled operator (about 10^3 at n = 64). The test measures kappa
+    on the oracle-side matrices and asserts the achieved error (against the
+    oracle's tight FP64 solution of the same FP32-rounded system, element by
+    element, column-scaled) is within max(1e-5, kappa u_32), u_32 = 2^-24."""
+    print(f"[pcg-dirichlet] cube{n} f32", flush=True)
+    m, K, M, mask, g, b = _cube_problem(n, "f32")
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    Kh, Mh, bh, gh = (t.double().cpu().numpy() for t in (K, M, b, g))
+    mh = mask.cpu().numpy()
+    u, rep = dgo.pcg(m, 0.0, M, 1.0, K, b, mask=mask, g=g, rtol=1e-8, max_iter=5000,
+                     stall_iters=30)
+    uo, _, _ = oracle.pcg(rp, col, 0.0, Mh, 1.0, Kh, bh, mask=mh, g=gh, rtol=1e-14,
+                          max_iter=20000)
+    kappa = _jacobi_condition(rp, col, 0.0, Mh, 1.0, Kh, mask=mh)
+    bound = max(RTOL["f32"], kappa * 2.0 ** -24)
+    w = assert_cols_close(u.double().cpu().numpy(), uo, bound)
+    print(f"  achieved {w:.2e}; kappa {kappa:.0f}; bound {bound:.2e}", flush=True)
+    bm = mh == 1
+    assert np.array_equal(u.double().cpu().numpy()[bm], gh[bm])
 
 
 def test_pcg_strict_and_deterministic():
@@ -354,9 +452,12 @@ def test_pcg_strict_and_deterministic():
     u2, _ = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-10)
     assert torch.equal(u1, u2)
     # a column solved alone agrees with the column solved in the block (the
-    # row split of the SpMV depends on k, so agreement is to rounding)
-    u0, _ = dgo.pcg(m, 1.0, M, 1e-3, K, b[:, 1].contiguous(), rtol=1e-10)
-    assert (u0 - u1[:, 1]).abs().max() <= 1e-9 * u1[:, 1].abs().max()
+    # row split of the SpMV depends on k, so agreement is to rounding), for
+    # the same iteration count
+    ub, _ = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=40, fixed_iters=True)
+    u0, _ = dgo.pcg(m, 1.0, M, 1e-3, K, b[:, 1].contiguous(), rtol=0.0, max_iter=40,
+                    fixed_iters=True)
+    assert_cols_close(u0.cpu().numpy(), ub[:, 1].cpu().numpy(), RTOL["f64"])
 
 
 def test_pcg_rtol_initial_matches_oracle():
@@ -378,6 +479,39 @@ def test_pcg_rtol_initial_matches_oracle():
         assert abs(int(rep["iters"][c]) - int(its[0])) <= 1
         rg = np.linalg.norm(bh[:, c] - A @ u.cpu().numpy()[:, c])
         assert rg <= 1.05e-4 * r0[c]
+
+
+def test_pcg_atol_matches_oracle():
+    """The absolute tolerance (Sec. 6.2's absolute and relative tolerances): a
+    column stops at ||r|| <= max(rtol ||b||, atol). With atol the larger
+    bound this is the oracle's relative stop at rtol = atol / ||b||; the
+    iteration counts agree within one and the solution equals the oracle's
+    iterate of the same count at 1e-12."""
+    print("[pcg] atol", flush=True)
+    m, K, M, b = _cfg2_system(4, 3, "f64")
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    Kh, Mh, bh = K.cpu().numpy(), M.cpu().numpy(), b.cpu().numpy()
+    bn = np.linalg.norm(bh, axis=0)
+    atol = 1e-6 * float(bn.min())
+    A = sp.csr_matrix((1e-3 * Kh, col, rp)) + sp.diags(Mh)
+    for rtol in (0.0, 1e-12):
+        u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=rtol, atol=atol, max_iter=2000)
+        assert rep["converged_all"], rep
+        for c in range(bh.shape[1]):
+            _, its, _ = oracle.pcg(rp, col, 1.0, Mh, 1e-3, Kh, bh[:, c].copy(),
+                                   rtol=atol / bn[c], max_iter=2000)
+            assert abs(int(rep["iters"][c]) - int(its[0])) <= 1, (rep["iters"], its)
+            rg = np.linalg.norm(bh[:, c] - A @ u.cpu().numpy()[:, c])
+            assert rg <= 1.05 * atol
+        ref = _oracle_same_iters(rp, col, 1.0, Mh, 1e-3, Kh, bh, rep["iters"])
+        assert_cols_close(u.cpu().numpy(), ref, RTOL["f64"])
+    # the relative bound is the larger one: atol has no effect
+    u1, r1 = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-6, atol=1e-30, max_iter=2000)
+    u2, r2 = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-6, max_iter=2000)
+    assert r1["iters"] == r2["iters"] and torch.equal(u1, u2)
+    with pytest.raises(dgo.DgoError) as e:
+        dgo.pcg(m, 1.0, M, 1e-3, K, b, atol=-1.0)
+    assert e.value.status == "INVALID_ARG"
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -458,40 +592,70 @@ def test_linear_solve_vjp_parity(dtype, with_f):
 def test_mcf_step_gradient_matches_oracle():
     """Autograd through AssembleFn and LinearSolveFn (forward PCG, adjoint PCG,
     solve VJP, assembly VJP) against the oracle's adjoint gradient of one
-    implicit MCF step."""
+    implicit MCF step. Both sides solve to their tightest tolerance, so the
+    comparison is bounded by the solves' accuracy: each converged solution is
+    within kappa * 1e-14 of the exact one (kappa about 10 for M + tau K at
+    this size), hence the bar 1e-12 on the loss and on the gradient."""
     print("[mcf-step] ico4 f64", flush=True)
     X, F = meshgen.icosphere(4, 1e-2, 10)
     tau = 1e-2
     W = meshgen.normal(24, X.size).reshape(X.shape)
     m = dgo.Mesh(torch.from_numpy(F).to(DEV), X.shape[0])
     Xd = torch.from_numpy(X).to(DEV).requires_grad_(True)
-    u = dgo.mcf_step(m, Xd, tau, rtol=1e-13, max_iter=5000)
+    u = dgo.mcf_step(m, Xd, tau, rtol=1e-14, max_iter=5000)
     loss = (u * torch.from_numpy(W).to(DEV)).sum()
     loss.backward()
     lo, go = oracle.mcf_step_grad(X, F, tau, W)
-    assert abs(loss.item() - lo) <= 1e-10 * abs(lo)
     g = Xd.grad.cpu().numpy()
-    assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
+    el = abs(loss.item() - lo) / abs(lo)
+    eg = np.abs(g - go).max() / np.abs(go).max()
+    print(f"  loss error {el:.2e}, gradient error {eg:.2e}", flush=True)
+    assert el <= RTOL["f64"] and eg <= RTOL["f64"]
 
 
-def test_autograd_loss_gradient_cfg5():
-    """loss = u^T K(x) u + total area through AssembleFn matches the oracle gradient."""
-    print("[autograd] batch of icosphere L5", flush=True)
-    B = 4
+def _cfg5_batch(dtype, B=256):
+    """Config 5: B icosphere L5 meshes with radial noise 1e-2 (seeds 0..B-1)
+    sharing one topology and one field u ~ N(0, 1) (seed 1000)."""
     X0, F = meshgen.icosphere(5)
     m = dgo.Mesh(torch.from_numpy(F).to(DEV), X0.shape[0])
     Xs = np.stack([meshgen.icosphere(5, 1e-2, s)[0] for s in range(B)])
-    u = meshgen.normal(1000, X0.shape[0])
-    X = torch.from_numpy(Xs).to(DEV).requires_grad_(True)
+    td = torch.float64 if dtype == "f64" else torch.float32
+    X = torch.from_numpy(Xs).to(DEV, td)
+    u = torch.from_numpy(meshgen.normal(1000, X0.shape[0])).to(DEV, td)
+    return m, F, X, u
+
+
+def _cfg5_loss(m, X, u):
+    """Per-mesh loss u^T K(x) u + total area through AssembleFn (torch only
+    forms the quadratic form from the CSR values the library returns)."""
     K, M = dgo.AssembleFn.apply(X, m)
-    ud = torch.from_numpy(u).to(DEV)
     rp, col = m.csr()
     rows = torch.repeat_interleave(torch.arange(m.nV, device=DEV), (rp[1:] - rp[:-1]).long())
-    quad = (K * (ud[rows] * ud[col.long()])[None, :]).sum(1)
-    loss = (quad + M.sum(1)).sum()
-    loss.backward()
-    for b in range(B):
-        Lo, go = oracle.loss_grad_tri(Xs[b], F, u)
-        assert abs(float((quad[b] + M[b].sum()).detach()) - Lo) <= 1e-12 * abs(Lo)
-        g = X.grad[b].cpu().numpy()
-        assert np.abs(g - go).max() <= 1e-12 * np.abs(go).max()
+    quad = (K * (u[rows] * u[col.long()])[None, :]).sum(1)
+    return quad + M.sum(1)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_autograd_loss_gradient_cfg5(dtype):
+    """Config 5 at full size (256 meshes of 10,242 vertices): loss and
+    gradient through AssembleFn against the oracle's direct loss gradient on
+    the same (in FP32: FP32-rounded) positions and field, each mesh's
+    gradient element by element at rtol * max |g*| of that mesh."""
+    print(f"[autograd] 256 x icosphere L5 {dtype}", flush=True)
+    m, F, X, u = _cfg5_batch(dtype)
+    X.requires_grad_(True)
+    loss = _cfg5_loss(m, X, u)
+    loss.sum().backward()
+    Xr = X.detach().double().cpu().numpy()
+    ur = u.double().cpu().numpy()
+    G = X.grad.double().cpu().numpy()
+    Lg = loss.detach().double().cpu().numpy()
+    worst = 0.0
+    for b in range(X.shape[0]):
+        Lo, go = oracle.loss_grad_tri(Xr[b], F, ur)
+        if dtype == "f64":  # in FP32 the loss value is torch's FP32 sum, not the library's
+            assert abs(Lg[b] - Lo) <= RTOL[dtype] * abs(Lo)
+        e = np.abs(G[b] - go)
+        assert np.all(e <= RTOL[dtype] * np.abs(go).max()), b
+        worst = max(worst, float(e.max() / np.abs(go).max()))
+    print(f"  worst gradient error {worst:.2e}", flush=True)

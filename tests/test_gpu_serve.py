@@ -8,10 +8,11 @@ import torch
 
 import meshgen
 import oracle
+from helpers import RTOL, assert_cols_close
 
 pytestmark = pytest.mark.gpu
 
-dgo = pytest.importorskip("paper_2602_12105_amd")
+import paper_2602_12105_amd as dgo  # noqa: E402  (no skip: a broken import fails the suite)
 from paper_2602_12105_amd.serve import Server, footprint  # noqa: E402
 
 ITERS = 50
@@ -67,10 +68,11 @@ def test_batched_matches_oracle_and_is_mix_independent():
         outs = [s.wait(t)[0].copy() for t in tickets]
         st = s.stats()
     assert st["completed"] == len(MIX) and st["failed"] == 0 and st["hbm_in_use"] == 0
+    worst = 0.0
     for (F, X, f), u in zip(reqs, outs):
         ref = _oracle(F, X, f)
-        err = np.abs(u.astype(np.float64) - ref).max() / np.abs(ref).max()
-        assert err <= 1e-4, err
+        worst = max(worst, assert_cols_close(u.astype(np.float64), ref, RTOL["f32"]))
+    print(f"  worst column-scaled error {worst:.2e}", flush=True)
     # alone: the same request on an otherwise empty server gives the same bits
     for i in (2, 5, 8):
         F, X, f = reqs[i]
@@ -88,8 +90,10 @@ def test_baseline_agrees_with_batched():
                     batched=batched) as s:
             ts = [s.submit(F, X, f) for F, X, f in reqs]
             outs[batched] = [s.wait(t)[0].copy() for t in ts]
-    for a, b in zip(outs[True], outs[False]):
-        assert np.abs(a - b).max() <= 1e-4 * np.abs(b).max()
+    for (F, X, f), a, b in zip(reqs, outs[True], outs[False]):
+        ref = _oracle(F, X, f)
+        assert_cols_close(a.astype(np.float64), ref, RTOL["f32"], "batched")
+        assert_cols_close(b.astype(np.float64), ref, RTOL["f32"], "one at a time")
 
 
 def test_continuous_batching_and_admission():
