@@ -333,6 +333,34 @@ dgo_status dgo_pcg(const dgo_mesh *mesh, dgo_dtype dtype, double alpha, const vo
                    int32_t k, const void *d_b, void *d_u, const dgo_cg_opts *opts,
                    dgo_cg_report *h_rep, dgo_stream stream);
 
+/* Allocation-free form of dgo_pcg with a fixed iteration count, for callers
+ * that cannot allocate device or host memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. It runs exactly
+ * `iters` Jacobi-PCG iterations (the fixed_iters mode of dgo_pcg: the same
+ * kernels, the same iterate bit for bit) on (alpha M + beta K) u = b with
+ * optional Dirichlet data (d_mask, d_g as in dgo_pcg), and only enqueues work
+ * on the stream: no host synchronisation, no progress polling, no report and
+ * no true-residual pass. Arguments, layouts and ownership are those of
+ * dgo_pcg (d_u holds the initial guess on entry, the iterate on exit).
+ * Its workspace (the PCG vectors, partial sums and per-column state) is a
+ * static device array of dgo_pcg_fixed_noalloc_max_bytes() = 128 MiB that
+ * each GPU the library runs on holds until the process ends; a mesh and
+ * column count needing more (dgo_pcg_fixed_noalloc_bytes) return
+ * DGO_ERR_UNSUPPORTED without enqueuing anything (about 78 MB for the
+ * icosphere of level 7 with 8 FP64 columns). The mesh must live on the
+ * current device (else DGO_ERR_INVALID_ARG). Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (two streams, two threads)
+ * race and must be serialised by the caller. Nothing in the array needs to
+ * start at zero. The mesh itself is created (and allocates) beforehand. */
+dgo_status dgo_pcg_fixed_noalloc(const dgo_mesh *mesh, dgo_dtype dtype, double alpha,
+                                 const void *d_Mdiag, double beta, const void *d_Kvals,
+                                 const uint8_t *d_mask, const void *d_g, int32_t k, const void *d_b,
+                                 void *d_u, int32_t iters, dgo_stream stream);
+/* Workspace bytes dgo_pcg_fixed_noalloc needs for this mesh, dtype and k (0
+ * for invalid arguments), and the size of its static array. Host only. */
+size_t dgo_pcg_fixed_noalloc_bytes(const dgo_mesh *mesh, dgo_dtype dtype, int32_t k);
+size_t dgo_pcg_fixed_noalloc_max_bytes(void);
+
 /* Gradients of a linear solve with respect to its operators: the adjoint
  * method (Sec. 3.1, Eq. implicit-full) applied to the linear relation
  * (alpha M + beta K) u - b = 0 of the solves of Sec. 5.2 (the implicit MCF

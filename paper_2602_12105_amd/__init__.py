@@ -22,7 +22,8 @@ from ._lib import (ARAP_CLAMP_MIN, DGO_F32, DGO_F64, AssembleOpts, CgOpts, CgRep
 __all__ = ["Mesh", "assemble", "assemble_vjp", "spmv", "pcg", "linear_solve_vjp", "AssembleFn",
            "LinearSolveFn", "mcf_step", "DgoError", "library_path", "build", "trace_enable",
            "trace_read", "trace_reset", "assemble_intrinsic", "face_gradient", "face_divergence",
-           "arap_laplacian", "conformal_laplacian", "eigs_smallest"]
+           "arap_laplacian", "conformal_laplacian", "eigs_smallest", "pcg_fixed_noalloc",
+           "pcg_fixed_noalloc_bytes"]
 
 
 def build():
@@ -331,6 +332,31 @@ def pcg(mesh: Mesh, alpha, M, beta, K, b, u0=None, mask=None, g=None, rtol=1e-8,
     report = {"converged_all": bool(rep.converged_all), "iters": list(rep.iters[:k]),
               "relres": list(rep.relres[:k]), "true_relres": list(rep.true_relres[:k])}
     return u, report
+
+
+def pcg_fixed_noalloc(mesh: Mesh, alpha, M, beta, K, b, u, iters, mask=None, g=None):
+    """Exactly `iters` PCG iterations on (alpha M + beta K) u = b into the
+    caller's u (initial guess on entry), with the library's static workspace:
+    no allocation and no host synchronisation (graph capture, serving loops).
+    Calls on one GPU must not overlap."""
+    _need(M, "M")
+    _need(K, "K", M.dtype)
+    _need(b, "b", M.dtype)
+    _need(u, "u", M.dtype, b.shape)
+    k = 1 if b.dim() == 1 else b.shape[1]
+    if mask is not None:
+        _need(mask, "mask", torch.uint8)
+        _need(g, "g", M.dtype, b.shape)
+    check(lib().dgo_pcg_fixed_noalloc(mesh.handle, _dtype_code(M.dtype), float(alpha), _ptr(M),
+                                      float(beta), _ptr(K), _ptr(mask), _ptr(g), k, _ptr(b),
+                                      _ptr(u), int(iters), _stream()), "dgo_pcg_fixed_noalloc")
+    return u
+
+
+def pcg_fixed_noalloc_bytes(mesh: Mesh, dtype, k):
+    """(bytes this solve needs, bytes the static workspace holds)."""
+    return (int(lib().dgo_pcg_fixed_noalloc_bytes(mesh.handle, _dtype_code(dtype), int(k))),
+            int(lib().dgo_pcg_fixed_noalloc_max_bytes()))
 
 
 def linear_solve_vjp(mesh: Mesh, alpha, beta, lam, u, f=None):

@@ -108,6 +108,9 @@ SIGNATURES = {
     "dgo_pcg": (C.c_int, [P, C.c_int, f64, P, f64, P, P, P, i32, P, P, C.POINTER(CgOpts),
                           C.POINTER(CgReport), P]),
     "dgo_linear_solve_vjp": (C.c_int, [P, C.c_int, f64, f64, i32, P, P, P, P, P, P]),
+    "dgo_pcg_fixed_noalloc": (C.c_int, [P, C.c_int, f64, P, f64, P, P, P, i32, P, P, i32, P]),
+    "dgo_pcg_fixed_noalloc_bytes": (C.c_size_t, [P, C.c_int, i32]),
+    "dgo_pcg_fixed_noalloc_max_bytes": (C.c_size_t, []),
     "dgo_trace_enable": (C.c_int, [i32, C.c_char_p]),
     "dgo_trace_read": (C.c_int, [C.POINTER(TraceEntry), i32, C.POINTER(i32)]),
     "dgo_trace_reset": (None, []),

@@ -41,6 +41,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 namespace dgo {
 namespace {
@@ -1046,7 +1047,7 @@ namespace {
 template <typename R>
 dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, const R *K,
                    const uint8_t *mask, const R *g, int k, const R *b, R *u, const dgo_cg_opts &o,
-                   dgo_cg_report *rep, hipStream_t s) {
+                   dgo_cg_report *rep, hipStream_t s, char *ws_given = nullptr) {
     const int64_t nV = m->nV, n = nV * k;
     const int KP = pow2ceil(k);
     // With a padded-row layout the iteration runs in the mesh's row order
@@ -1054,8 +1055,8 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     const bool ell = m->ell_w > 0;
     const int64_t nvals = ell ? nV * m->ell_w : m->nnz;
     const PcgLayout L = pcg_layout(nV, nvals, k, sizeof(R));
-    void *wsv;
-    DGO_TRY(mesh_workspace(const_cast<dgo_mesh *>(m), L.total, s, &wsv));
+    void *wsv = ws_given;
+    if (!ws_given) DGO_TRY(mesh_workspace(const_cast<dgo_mesh *>(m), L.total, s, &wsv));
     char *ws = (char *)wsv;
     R *r = (R *)(ws + L.off_r), *p = (R *)(ws + L.off_p), *sv = (R *)(ws + L.off_s);
     R *w = (R *)(ws + L.off_w);
@@ -1133,6 +1134,29 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
             nbs = launch_sdot<R>(m, v, dvec, k, r, w, stt[i & 1], part2, st_s);
         }
     };
+    auto unorder = [&](int32_t done) {
+        if (ell)
+            DGO_LAUNCH("cg_unorder", s,
+                       k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, m->order, stt[done & 1],
+                                                                     p, x, u));
+        else
+            DGO_LAUNCH("cg_unorder", s,
+                       k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, nullptr, stt[done & 1],
+                                                                     p, x, x));
+    };
+    if (ws_given) {
+        // the allocation-free form (a fixed iteration count): every
+        // iteration is queued at once, with no progress polling, no true
+        // residual and nothing read back to the host
+        const int32_t iters = std::max<int32_t>(o.max_iter, 0);
+        iterate(s, 0, iters);
+        if (iters > 0)
+            launch_fin<FIN_SR_ITER>(partU[iters & 1], (int)nb_v, part2, nbs, k, stt[(iters + 1) & 1],
+                                    stt[iters & 1], prm, nullptr, s);
+        unorder(iters);
+        DGO_HIP(hipGetLastError());
+        return DGO_OK;
+    }
     // Progress polling without idling the device: up to two chunks are in
     // flight, so the next one is queued before the host waits for the state
     // copied after the previous one. Once every column has stopped, queued
@@ -1207,14 +1231,7 @@ dgo_status run_pcg(const dgo_mesh *m, double alpha, const R *M, double beta, con
     if (done_iters > 0)
         launch_fin<FIN_SR_ITER>(partU[done_iters & 1], (int)nb_v, part2, nbs, k,
                                 stt[(done_iters + 1) & 1], stt[done_iters & 1], prm, nullptr, s);
-    if (ell)
-        DGO_LAUNCH("cg_unorder", s,
-                   k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, m->order, stt[done_iters & 1],
-                                                                 p, x, u));
-    else
-        DGO_LAUNCH("cg_unorder", s,
-                   k_cg_finish_x<R><<<grid_for(n, T), T, 0, s>>>(n, k, nullptr, stt[done_iters & 1],
-                                                                 p, x, x));
+    unorder(done_iters);
     // the true residual: FP64 solves with the SpMV's lane groups, FP32 ones
     // with one thread per (row, column) accumulating in FP64
     int nb_tr = (int)nb_t;
@@ -1359,4 +1376,88 @@ extern "C" dgo_status dgo_linear_solve_vjp(const dgo_mesh *m, dgo_dtype dtype, d
                        (float *)d_gK, (float *)d_gM));
     DGO_HIP(hipGetLastError());
     return DGO_OK;
+}
+
+// ------------------------------------------------ allocation-free PCG form
+
+namespace {
+
+// Workspace of dgo_pcg_fixed_noalloc: one static device array per GPU the
+// library runs on (held until the process ends). Host code never passes the
+// array's name to a kernel: it takes the array's device address from
+// hipGetSymbolAddress, once per device, and passes that.
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch` (looked up on the first call on
+// that device, with the device current).
+dgo_status scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(DGO_ERR_UNSUPPORTED, "dgo_pcg_fixed_noalloc: device ordinal above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+        if (!p) return fail(DGO_ERR_DEVICE, "dgo_pcg_fixed_noalloc: no scratch address");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DGO_OK;
+}
+
+}  // namespace
+
+extern "C" size_t dgo_pcg_fixed_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+extern "C" size_t dgo_pcg_fixed_noalloc_bytes(const dgo_mesh *m, dgo_dtype dtype, int32_t k) {
+    if (!m || k < 1 || k > kMaxK || (dtype != DGO_F32 && dtype != DGO_F64)) return 0;
+    const int64_t nvals = m->ell_w > 0 ? (int64_t)m->nV * m->ell_w : m->nnz;
+    return pcg_layout(m->nV, nvals, k, dtype == DGO_F64 ? 8 : 4).total;
+}
+
+extern "C" dgo_status dgo_pcg_fixed_noalloc(const dgo_mesh *m, dgo_dtype dtype, double alpha,
+                                            const void *d_Mdiag, double beta, const void *d_Kvals,
+                                            const uint8_t *d_mask, const void *d_g, int32_t k,
+                                            const void *d_b, void *d_u, int32_t iters,
+                                            dgo_stream stream) {
+    clear_error();
+    if (!m || !d_Mdiag || !d_Kvals || !d_b || !d_u)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_pcg_fixed_noalloc: NULL argument");
+    if (k < 1 || k > kMaxK) return fail(DGO_ERR_INVALID_ARG, "dgo_pcg_fixed_noalloc: k must be in [1, 64]");
+    if (iters < 0) return fail(DGO_ERR_INVALID_ARG, "dgo_pcg_fixed_noalloc: iters must be >= 0");
+    if (d_mask && !d_g) return fail(DGO_ERR_INVALID_ARG, "dgo_pcg_fixed_noalloc: mask given without g");
+    if (dtype != DGO_F32 && dtype != DGO_F64)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_pcg_fixed_noalloc: bad dtype");
+    if (!m->rdesc || !m->rlen)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_pcg_fixed_noalloc: mesh was built without SpMV row descriptors");
+    int dev = 0;
+    DGO_HIP(hipGetDevice(&dev));
+    if (dev != m->device)
+        return fail(DGO_ERR_INVALID_ARG, "dgo_pcg_fixed_noalloc: the mesh lives on another device");
+    const size_t need = dgo_pcg_fixed_noalloc_bytes(m, dtype, k);
+    if (need > kNoAllocScratchBytes)
+        return fail(DGO_ERR_UNSUPPORTED,
+                    "dgo_pcg_fixed_noalloc: this mesh and column count need " + std::to_string(need) +
+                        " bytes of workspace; the static scratch holds " +
+                        std::to_string(kNoAllocScratchBytes) + " (use dgo_pcg)");
+    void *ws = nullptr;
+    DGO_TRY(scratch_address(dev, &ws));
+    dgo_cg_opts o{};
+    o.rtol = 0.0;
+    o.max_iter = iters;
+    o.fixed_iters = 1;
+    o.check_every = iters > 0 ? iters : 1;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == DGO_F64)
+        return run_pcg<double>(m, alpha, (const double *)d_Mdiag, beta, (const double *)d_Kvals,
+                               d_mask, (const double *)d_g, k, (const double *)d_b, (double *)d_u, o,
+                               nullptr, s, (char *)ws);
+    return run_pcg<float>(m, alpha, (const float *)d_Mdiag, beta, (const float *)d_Kvals, d_mask,
+                          (const float *)d_g, k, (const float *)d_b, (float *)d_u, o, nullptr, s,
+                          (char *)ws);
 }
