@@ -248,7 +248,7 @@ k_vjp_rows(AsmView v, const int32_t *__restrict__ diag, const int32_t *__restric
     __syncthreads();
     for (int32_t q = t; q < ninc; q += blockDim.x) {
         const uint32_t rec = lrec[q];
-        const int32_t rr = row_of(lvt, nrows, q);
+        const int32_t rr = rec_row(rec, rpb);
         const int32_t base = lrp[rr];
         const int32_t la = base + (int32_t)(rec & 255u), lb = base + (int32_t)((rec >> 8) & 255u);
         const int32_t a = lcol[la], b = lcol[lb];

@@ -85,7 +85,7 @@ __global__ void k_inc_tslot(const int32_t *__restrict__ inc_elem, const uint32_t
                             int64_t n_inc, int64_t nF, int32_t *__restrict__ tslot) {
     const int64_t q = (int64_t)blockIdx.x * kFaceThreads + threadIdx.x;
     if (q >= n_inc) return;
-    tslot[q] = (int32_t)((int64_t)(inc[q] >> 24) * nF + inc_elem[q]);
+    tslot[q] = (int32_t)((int64_t)((inc[q] >> 24) & 3u) * nF + inc_elem[q]);
 }
 
 template <typename R>

@@ -216,11 +216,10 @@ size_t scan_tmp_elems(int64_t n);
 dgo_status exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp,
                           hipStream_t s);
 
-// Row blocks of the assembly kernels: rows per workgroup (before halving to
-// fit the LDS budget) and the LDS a block needs: the block's CSR span
-// (values, column ids and the column vertices' positions), one record and CW
-// contributions per incidence, the block's own positions, and the block's row
-// and incidence offsets.
+// Row blocks of the assembly kernels: rows per workgroup (a power of two of
+// at most 64, halved to fit the LDS budget) and the LDS a block needs: the
+// block's CSR span (values and column ids), one record and CW contributions
+// per incidence, and the block's row and incidence offsets.
 constexpr int32_t kRowsPerBlockTri = 64;
 constexpr int32_t kRowsPerBlockTet = 16;
 constexpr int64_t kRowBlockLdsBytes = 64 * 1024;
@@ -228,7 +227,7 @@ constexpr int kAssembleThreads = 256;
 
 inline int64_t assembly_lds_bytes(int dim, int s, int64_t rpb, int64_t span, int64_t ninc) {
     const int cw = dim == 2 ? 3 : 4;
-    return span * (s + 4) + ninc * (cw * s + 4) + rpb * 3 * s + 2 * (rpb + 1) * 4 + 64;
+    return span * (s + 4) + ninc * (cw * s + 4) + 2 * (rpb + 1) * 4 + 64;
 }
 
 inline unsigned grid_for(int64_t n, int threads) {

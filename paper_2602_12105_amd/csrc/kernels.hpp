@@ -126,18 +126,17 @@ __device__ __forceinline__ V3<R> sel2v(bool c, V3<R> a, V3<R> b) {
 // touching consecutive entries hit consecutive banks:
 //   acc  : R[span]          the block's CSR values (accumulated, then finished)
 //   cw   : R[CW][inc_max]   per-incidence contributions (phase A)
-//   xo   : R[3][rpb]        positions of the block's own vertices
 //   lcol : int32[span]      the block's column ids
 //   lrec : uint32[ninc]     the block's incidence records
 //   lrp  : int32[rpb + 1]   row offsets into the span
 //   lvt  : int32[rpb + 1]   row offsets into the incidence records
-// The other vertices' positions are gathered from X in phase A (they are
-// L2-resident: each is read by the few rows around it). Staging them in LDS
-// too was measured slower: the larger footprint allowed fewer resident
-// workgroups, and the kernel is bound by load latency, not by L2 traffic.
+// The element's vertex positions are gathered from X in phase A (they are
+// L1/L2-resident: each is read by the few rows around it). Staging every
+// span entry's position in LDS was measured slower: the larger footprint
+// allowed fewer resident workgroups.
 template <typename R, int CW>
 struct BlockLds {
-    R *acc, *cw, *xo;
+    R *acc, *cw;
     int32_t *lcol, *lrp, *lvt;
     uint32_t *lrec;
     int32_t inc_max, span_max, rpb;
@@ -145,24 +144,19 @@ struct BlockLds {
         : inc_max(inc_max_), span_max(span_max_), rpb(rpb_) {
         acc = (R *)smem;
         cw = acc + span_max;
-        xo = cw + (size_t)inc_max * CW;
-        lcol = (int32_t *)(xo + (size_t)rpb * 3);
+        lcol = (int32_t *)(cw + (size_t)inc_max * CW);
         lrec = (uint32_t *)(lcol + span_max);
         lrp = (int32_t *)(lrec + inc_max);
         lvt = lrp + rpb + 1;
     }
     __device__ R &c(int f, int32_t q) { return cw[(size_t)f * inc_max + q]; }
-    __device__ V3<R> own(int32_t r) const { return {xo[r], xo[rpb + r], xo[2 * rpb + r]}; }
 };
 
-// Row of incidence q within the block: the r with lvt[r] <= q < lvt[r + 1].
-__device__ __forceinline__ int32_t row_of(const int32_t *lvt, int32_t nrows, int32_t q) {
-    int32_t lo = 0, hi = nrows;  // invariant: lvt[lo] <= q < lvt[hi]
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (lvt[mid] <= q) lo = mid; else hi = mid;
-    }
-    return lo;
+// Row of an incidence record within its block: the record carries its
+// vertex modulo 64 (bits 26-31), and blocks hold a power of two of at most
+// 64 rows starting at a multiple of that size.
+__device__ __forceinline__ int32_t rec_row(uint32_t rec, int32_t rpb) {
+    return (int32_t)((rec >> 26) & (uint32_t)(rpb - 1));
 }
 
 // Phase A runs one thread per (vertex, element) incidence of the block and
@@ -255,11 +249,6 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
         L.lrp[j] = rowptr[r0 + j] - s0;
         L.lvt[j] = vtptr[r0 + j] - q0;
     }
-    if (!INTR)
-        for (int32_t j = t; j < 3 * nrows; j += blockDim.x) {
-            const int32_t r = j / 3, c = j - 3 * r;
-            L.xo[c * rpb + r] = X[3 * (int64_t)r0 + j];
-        }
     for (int32_t j = t; j < span; j += blockDim.x) {
         const int32_t c = col[s0 + j];
         L.lcol[j] = c;
@@ -271,13 +260,13 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
     // phase A: element terms per incidence, from LDS only
     for (int32_t q = t; q < ninc; q += blockDim.x) {
         const uint32_t rec = L.lrec[q];
-        const int32_t rr = row_of(L.lvt, nrows, q);
+        const int32_t rr = rec_row(rec, rpb);
         const int32_t i = r0 + rr, base = L.lrp[rr];
         const int32_t la = base + (int32_t)(rec & 255u), lb = base + (int32_t)((rec >> 8) & 255u);
         if constexpr (INTR) {
             // triangle (i, a, b) in cyclic order; edge ids by the rule that
             // slot j of a triangle is the edge opposite its vertex j
-            const int p = (int)(rec >> 24);
+            const int p = (int)((rec >> 24) & 3u);
             const int32_t *fe = elem_edge + 3 * (int64_t)inc_elem[q0 + q];
             const int pa = p == 2 ? 0 : p + 1, pb = p == 0 ? 2 : p - 1;
             const R ei = X[fe[p]], ea = X[fe[pa]], eb = X[fe[pb]];  // opposite i, a, b
@@ -286,44 +275,56 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             if (A == R(0) && i < L.lcol[la] && i < L.lcol[lb]) ++ndeg;
             continue;
         }
-        const V3<R> xi = L.own(rr);
         if (DIM == 2) {
             const int32_t a = L.lcol[la], b = L.lcol[lb];
-            const V3<R> xa = ld3(X, a), xb = ld3(X, b);
             // |n| = 2 area is shared by the triangle's three cotangents,
-            // cot = (e1 . e2) / |n|; n is formed from the vertices in id
-            // order and each dot product from the edge's endpoints in id
-            // order, so every row that needs a value computes the same bits
-            // (K stays exactly symmetric)
+            // cot = (e1 . e2) / |n|; the positions are gathered in vertex-id
+            // order (the ids are sorted, not the positions), n is formed from
+            // them in that order and each corner's dot product from the
+            // other two in that order, so every row that needs a value
+            // computes the same bits (K stays exactly symmetric)
             const bool ia = i < a, ib = i < b, ab = a < b;
-            const V3<R> v0 = ia ? (ib ? xi : xb) : (ab ? xa : xb);
-            const V3<R> v2 = ia ? (ab ? xb : xa) : (ib ? xb : xi);
+            const int32_t u0 = ia ? (ib ? i : b) : (ab ? a : b);
+            const int32_t u2 = ia ? (ab ? b : a) : (ib ? b : i);
             // the middle one: i if it lies between a and b, else the smaller
             // of a, b when i is the smallest and the larger when i is largest
-            const V3<R> v1 = ia != ib ? xi : (ia == ab ? xa : xb);
+            const int32_t u1 = ia != ib ? i : (ia == ab ? a : b);
+            const V3<R> v0 = ld3(X, u0), v1 = ld3(X, u1), v2 = ld3(X, u2);
             const V3<R> n = cross(sub(v1, v0), sub(v2, v0));
             const R n2 = dot(n, n);
             const R nn = sqrt(n2);
             const R h = R(0.5) / nn;
+            // the corner dot products at the sorted vertices
+            const R d0 = dot(sub(v1, v0), sub(v2, v0));
+            const R d1 = dot(sub(v0, v1), sub(v2, v1));
+            const R d2 = dot(sub(v0, v2), sub(v1, v2));
             // edge (i, a) is opposite b, edge (i, b) is opposite a
-            const R db = ia ? dot(sub(xi, xb), sub(xa, xb)) : dot(sub(xa, xb), sub(xi, xb));
-            const R da = ib ? dot(sub(xi, xa), sub(xb, xa)) : dot(sub(xb, xa), sub(xi, xa));
+            const int kb = (b > a) + (b > i), ka = (a > b) + (a > i);
+            const R db = kb == 0 ? d0 : (kb == 1 ? d1 : d2);
+            const R da = ka == 0 ? d0 : (ka == 1 ? d1 : d2);
             L.c(0, q) = db * h;
             L.c(1, q) = da * h;
-            L.c(2, q) = mass_kind == 1
-                            ? voronoi_corner(sub(xa, xi), sub(xb, xi), nn, db * h, da * h, db, da)
-                            : nn / R(6);
+            if (mass_kind == 1) {
+                const int ki = (i > a) + (i > b);
+                const V3<R> xi = sel2v(ki == 0, v0, sel2v(ki == 1, v1, v2));
+                const V3<R> xa = sel2v(ka == 0, v0, sel2v(ka == 1, v1, v2));
+                const V3<R> xb = sel2v(kb == 0, v0, sel2v(kb == 1, v1, v2));
+                L.c(2, q) = voronoi_corner(sub(xa, xi), sub(xb, xi), nn, db * h, da * h, db, da);
+            } else {
+                L.c(2, q) = nn / R(6);
+            }
             if (n2 == R(0) && ia && ib) ++ndeg;
         } else {
-            const int p = (int)(rec >> 24);
+            const int p = (int)((rec >> 24) & 3u);
             const int32_t lc = base + (int32_t)((rec >> 16) & 255u);
             const int32_t w0 = L.lcol[la], w1 = L.lcol[lb], w2 = L.lcol[lc];
-            const V3<R> y0 = ld3(X, w0), y1 = ld3(X, w1), y2 = ld3(X, w2);
-            // element order: i sits at position p, the others follow in order
-            const V3<R> x0 = sel2v(p == 0, xi, y0);
-            const V3<R> x1 = sel2v(p == 0, y0, sel2v(p == 1, xi, y1));
-            const V3<R> x2 = sel2v(p <= 1, y1, sel2v(p == 2, xi, y2));
-            const V3<R> x3 = sel2v(p <= 2, y2, xi);
+            // element order: i sits at position p, the others follow in
+            // order; the ids are placed, then the positions gathered
+            const int32_t id0 = p == 0 ? i : w0;
+            const int32_t id1 = p == 0 ? w0 : (p == 1 ? i : w1);
+            const int32_t id2 = p <= 1 ? w1 : (p == 2 ? i : w2);
+            const int32_t id3 = p <= 2 ? w2 : i;
+            const V3<R> x0 = ld3(X, id0), x1 = ld3(X, id1), x2 = ld3(X, id2), x3 = ld3(X, id3);
             const TetG<R> tg = tet_grads(x0, x1, x2, x3);
             // every pair's product in one fixed operand order, then the three
             // pairs (p, other) in element order

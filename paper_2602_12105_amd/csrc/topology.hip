@@ -219,7 +219,8 @@ __device__ __forceinline__ int32_t local_col(const int32_t *col, int32_t b, int3
 // Incidence record of vertex v in element el (sorted by element id):
 //   bits 0-7, 8-15, 16-23: row-local CSR column indices of the other vertices
 //   of the element, in element order after v (triangles: cyclic (v, a, b);
-//   tetrahedra: local order skipping v); bits 24-25: v's local position.
+//   tetrahedra: local order skipping v); bits 24-25: v's local position;
+//   bits 26-31: v modulo 64 (the row within its block of rows).
 __global__ void k_inc_pack(const int32_t *elem, int nv, const int32_t *vtptr,
                            const int32_t *inc_elem, const int32_t *rowptr, const int32_t *col,
                            int32_t nV, uint32_t *rec) {
@@ -231,7 +232,7 @@ __global__ void k_inc_pack(const int32_t *elem, int nv, const int32_t *vtptr,
         int p = 0;
         for (int a = 0; a < nv; ++a)
             if (el[a] == v) p = a;
-        uint32_t r = (uint32_t)p << 24;
+        uint32_t r = ((uint32_t)p << 24) | ((uint32_t)(v & 63) << 26);
         if (nv == 3) {
             int32_t la = local_col(col, rb, re, el[(p + 1) % 3]) - rb;
             int32_t lb = local_col(col, rb, re, el[(p + 2) % 3]) - rb;
