@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-suite", action="store_true",
                     help="skip the other workloads (tets, grid, VJP batch, size sweep)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--no-extra-steps", action="store_true",
+                    help="skip the past-cache (L9) and other-precision PCG steps")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--serve-pool", type=int, default=256,
                     help="distinct generated payloads the arrivals are drawn from")
@@ -158,91 +160,38 @@ def main():
     td = torch.float64 if args.dtype == "f64" else torch.float32
     s = 8 if args.dtype == "f64" else 4
     k = 8
-    log(args, "generating icosphere level", args.level)
-    X, F = meshgen.icosphere(args.level, 1e-3, 0)
-    f = meshgen.normal(1, X.shape[0] * k).reshape(-1, k)
-    nV, nF = X.shape[0], F.shape[0]
+    head = pcg_step(args, dgo, torch, meshgen, args.level, args.dtype, args.steps, args.warmup)
+    mesh, Xd, fd, K, M = head.pop("_objects")
+    X, F, f = head.pop("_host")
+    nV, nF, nnz = mesh.nV, mesh.n_elem, mesh.nnz
+    value, ms_per_step, roofline = head["value"], head["ms_per_step"], head["roofline"]
+    roofline["regime"] = ("effective: measured in the solve loop, whose working set "
+                          f"({head['working_set_mb']:.0f} MB) stays in the 256 MB last-level "
+                          "cache; the HBM fractions past the cache are under past_cache")
 
-    Fd = torch.from_numpy(F).to(dev)
-    Xd = torch.from_numpy(X).to(dev, td)
-    fd = torch.from_numpy(f).to(dev, td)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mesh = dgo.Mesh(Fd, nV)
-    torch.cuda.synchronize()
-    topo_ms = (time.perf_counter() - t0) * 1e3
-    nnz = mesh.nnz
-    K = torch.empty(nnz, dtype=td, device=dev)
-    M = torch.empty(nV, dtype=td, device=dev)
-    b = torch.empty_like(fd)
-    u0 = torch.zeros_like(fd)
-    rtol = 1e-8
-    stall = 20 if args.dtype == "f32" else 0
-    reports = []
-
-    def step():
-        dgo.assemble(mesh, Xd, out=(K, M))
-        dgo.spmv(mesh, 1.0, M, 0.0, K, fd, out=b)  # b = M f
-        u, rep = dgo.pcg(mesh, 1.0, M, 1e-3, K, b, u0=u0, rtol=rtol, max_iter=1000,
-                         check_every=8, stall_iters=stall)
-        reports.append(rep)
-        return u
-
-    log(args, f"topology {topo_ms:.1f} ms; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    reports.clear()
-    log(args, f"timed {args.steps} steps")
-    # nothing is timed per kernel inside the timed steps: even the events a
-    # launch carries itself slowed the step by about 14% (measured)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        u = step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall / args.steps * 1e3
-    value = nF * args.steps / wall
-    iters = reports[-1]["iters"]
-    true_rr = max(reports[-1]["true_relres"])
-
-    # second pass: the same steps with every library kernel timed (the
-    # reported ones by their dispatch events, the others bracketed by events)
-    log(args, "traced pass")
-    dgo.trace_reset()
-    dgo.trace_enable(True)
-    torch.cuda.synchronize()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dgo.trace_enable(False)
-    tr = dgo.trace_read()
-    # The solver queues the next chunk of iterations before it has seen the
-    # previous one finish (it never waits on the host), so each solve ends
-    # with launches that find every column stopped and exit at once. Their
-    # time is charged to the iterations that did work: the per-launch figures
-    # of the iteration kernels divide by the iterations run, not the launches.
-    maxit = max(iters)
-    effective = {"cg_vupdate": maxit, "cg_sdot": maxit + 1}
-    kernels = {}
-    for n, e in tr.items():
-        ab = alg_bytes(n, s, nV, nF, nnz, k)
-        per_step = e["count"] / args.steps
-        n_eff = effective.get(n, per_step)
-        ent = {"launches_per_step": per_step, "effective_launches_per_step": n_eff,
-               "avg_us": e["total_ms"] / args.steps / n_eff * 1e3,
-               "ms_per_step": e["total_ms"] / args.steps}
-        if ab is not None and ent["avg_us"] > 0:
-            gbs = ab / (ent["avg_us"] * 1e-6) / 1e9
-            ent.update({"alg_bytes": ab, "gbps": gbs, "frac": gbs / HBM_PEAK_GBS})
-        kernels[n] = ent
-    dom = max((n for n in kernels if "gbps" in kernels[n]), key=lambda n: kernels[n]["ms_per_step"])
-    dk = kernels[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["gbps"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": dk["frac"],
-                "traffic": measured_traffic(dom, args.dtype, args.level),
-                "alg_bytes_per_launch": dk["alg_bytes"], "avg_us": dk["avg_us"]}
+    # the same step past the last-level cache (icosphere L9, 2.6 M vertices,
+    # 8 columns; working set about 1.1 GB in FP64): the dominant kernel's
+    # fraction there is an HBM figure
+    past = {}
+    for dt in (() if args.no_extra_steps else ("f64", "f32")):
+        log(args, f"PCG step past the cache: icosphere L9 {dt}")
+        r = pcg_step(args, dgo, torch, meshgen, 9, dt, max(3, args.steps // 4), 1)
+        r.pop("_objects")
+        r.pop("_host")
+        past[f"icosphere_L9_{dt}"] = r
+        torch.cuda.empty_cache()
+    if past:
+        roofline["past_cache"] = {"workload": "the same step on icosphere L9 (2,621,442 V, "
+                                              "5,242,880 F), 8 RHS, rtol 1e-8",
+                                  "f64": past["icosphere_L9_f64"]["roofline"],
+                                  "f32": past["icosphere_L9_f32"]["roofline"]}
+        # the headline workload in the other precision
+        other = "f32" if args.dtype == "f64" else "f64"
+        log(args, f"PCG step icosphere L{args.level} {other}")
+        r = pcg_step(args, dgo, torch, meshgen, args.level, other, args.steps, args.warmup)
+        r.pop("_objects")
+        r.pop("_host")
+        past[f"icosphere_L{args.level}_{other}"] = r
 
     # kernel-level rooflines outside the solve: assembly and SpMM (k = 8 and 1),
     # warm (back to back) and cold (1 GiB written between launches)
@@ -316,9 +265,10 @@ def main():
                                "8 RHS, rtol 1e-8",
                    "nV": nV, "nF": nF, "nnz": nnz, "k": k, "parallelism": "single GPU"},
         "roofline": roofline,
-        "pcg": {"iters": iters, "max_true_relres": true_rr},
-        "topology_ms": topo_ms,
-        "kernels": kernels,
+        "pcg": {"iters": head["iters"], "max_true_relres": head["max_true_relres"]},
+        "topology_ms": head["topology_ms"],
+        "kernels": head["kernels"],
+        "pcg_steps": past,
         "kernel_sweeps": sweeps,
         "stream_copy_gbps": copy_gbs,
         "baseline_note": PAPER_NOTE,
@@ -338,6 +288,106 @@ def main():
             torch.add(a, 1.0, out=b_)
         torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
+
+
+def pcg_step(args, dgo, torch, meshgen, level, dtype, steps, warmup):
+    """One step of the headline workload on the icosphere of `level`: assemble
+    K and M, b = M f, Jacobi PCG on (M + 1e-3 K) u = b to rtol 1e-8 on 8
+    columns. Times `steps` steps (after `warmup`), then the same steps again
+    with every library kernel timed; returns the step rate, the per-kernel
+    table and the dominant kernel's roofline."""
+    dev = torch.device("cuda:0")
+    td = torch.float64 if dtype == "f64" else torch.float32
+    s = 8 if dtype == "f64" else 4
+    k = 8
+    log(args, f"generating icosphere level {level}")
+    X, F = meshgen.icosphere(level, 1e-3, 0)
+    f = meshgen.normal(1, X.shape[0] * k).reshape(-1, k)
+    nV, nF = X.shape[0], F.shape[0]
+    Fd = torch.from_numpy(F).to(dev)
+    Xd = torch.from_numpy(X).to(dev, td)
+    fd = torch.from_numpy(f).to(dev, td)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mesh = dgo.Mesh(Fd, nV)
+    torch.cuda.synchronize()
+    topo_ms = (time.perf_counter() - t0) * 1e3
+    nnz = mesh.nnz
+    K = torch.empty(nnz, dtype=td, device=dev)
+    M = torch.empty(nV, dtype=td, device=dev)
+    b = torch.empty_like(fd)
+    u0 = torch.zeros_like(fd)
+    stall = 20 if dtype == "f32" else 0
+    reports = []
+
+    def step():
+        dgo.assemble(mesh, Xd, out=(K, M))
+        dgo.spmv(mesh, 1.0, M, 0.0, K, fd, out=b)  # b = M f
+        u, rep = dgo.pcg(mesh, 1.0, M, 1e-3, K, b, u0=u0, rtol=1e-8, max_iter=1000,
+                         check_every=8, stall_iters=stall)
+        reports.append(rep)
+        return u
+
+    log(args, f"L{level} {dtype}: topology {topo_ms:.1f} ms; warmup {warmup}")
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    reports.clear()
+    log(args, f"L{level} {dtype}: timed {steps} steps")
+    # nothing is timed per kernel inside the timed steps: even the events a
+    # launch carries itself slowed the step by about 14% (measured)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    iters = reports[-1]["iters"]
+    true_rr = max(reports[-1]["true_relres"])
+
+    # second pass: the same steps with every library kernel timed (the
+    # reported ones by their dispatch events, the others bracketed by events)
+    dgo.trace_reset()
+    dgo.trace_enable(True)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dgo.trace_enable(False)
+    tr = dgo.trace_read()
+    # The solver queues the next chunk of iterations before it has seen the
+    # previous one finish (it never waits on the host), so each solve ends
+    # with launches that find every column stopped and exit at once. Their
+    # time is charged to the iterations that did work: the per-launch figures
+    # of the iteration kernels divide by the iterations run, not the launches.
+    maxit = max(iters)
+    effective = {"cg_vupdate": maxit, "cg_sdot": maxit + 1}
+    kernels = {}
+    for n, e in tr.items():
+        ab = alg_bytes(n, s, nV, nF, nnz, k)
+        per_step = e["count"] / steps
+        n_eff = effective.get(n, per_step)
+        ent = {"launches_per_step": per_step, "effective_launches_per_step": n_eff,
+               "avg_us": e["total_ms"] / steps / n_eff * 1e3,
+               "ms_per_step": e["total_ms"] / steps}
+        if ab is not None and ent["avg_us"] > 0:
+            gbs = ab / (ent["avg_us"] * 1e-6) / 1e9
+            ent.update({"alg_bytes": ab, "gbps": gbs, "frac": gbs / HBM_PEAK_GBS})
+        kernels[n] = ent
+    dom = max((n for n in kernels if "gbps" in kernels[n]), key=lambda n: kernels[n]["ms_per_step"])
+    dk = kernels[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["gbps"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dk["frac"],
+                "traffic": measured_traffic(dom, dtype, level),
+                "alg_bytes_per_launch": dk["alg_bytes"], "avg_us": dk["avg_us"]}
+    # the PCG loop's resident data: K values and pattern (padded rows), D^-1,
+    # and the vectors r p s w x b (nV x k each)
+    ws_mb = (nV * 8 * (s + 4) + 2 * s * nV + 6 * k * s * nV) / 1e6
+    return {"level": level, "dtype": dtype, "nV": nV, "nF": nF, "nnz": nnz, "k": k,
+            "steps": steps, "value_triangles_per_s": nF * steps / wall, "value": nF * steps / wall,
+            "ms_per_step": wall / steps * 1e3, "iters": iters, "max_true_relres": true_rr,
+            "topology_ms": topo_ms, "working_set_mb": ws_mb, "kernels": kernels,
+            "roofline": roofline, "_objects": (mesh, Xd, fd, K, M), "_host": (X, F, f)}
 
 
 def kernel_time(dgo, torch, fn, name, reps, flush=None):
@@ -394,41 +444,48 @@ def suite(args, dgo, torch, meshgen):
     out = {}
     td, s = (torch.float64, 8) if args.dtype == "f64" else (torch.float32, 4)
 
-    # tetrahedral volume: Kuhn cube 64^3, jitter 0.15 h, Dirichlet Poisson to 1e-8
-    log(args, "suite: Kuhn cube 64^3")
+    # tetrahedral volume: Kuhn cube 64^3, jitter 0.15 h, Dirichlet Poisson to 1e-8,
+    # in both precisions
     import numpy as np
     X, T = meshgen.cube_tets(64, 0.15, 0)
     m = dgo.Mesh(torch.from_numpy(T).to(dev), X.shape[0])
-    Xd = torch.from_numpy(X).to(dev, td)
-    K, M = dgo.assemble(m, Xd)
-    ent = {"nV": m.nV, "nT": m.n_elem, "nnz": m.nnz}
-    ab = alg_bytes("assemble_tet", s, m.nV, m.n_elem, m.nnz, 1)
-    for cold in (False, True):
-        us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xd, out=(K, M)), "assemble_tet", reps,
-                         flush if cold else None)
-        ent["assemble_" + ("cold" if cold else "warm")] = roof(ab, us)
-    ent["tets_per_s_cold"] = m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
-    x1 = torch.rand(m.nV, dtype=td, device=dev)
-    y1 = torch.empty_like(x1)
-    ab = alg_bytes("spmm", s, m.nV, m.n_elem, m.nnz, 1)
-    for cold in (False, True):
-        us = kernel_time(dgo, torch, lambda: dgo.spmv(m, 0.0, M, 1.0, K, x1, out=y1), "spmm", reps,
-                         flush if cold else None)
-        ent["spmv_k1_" + ("cold" if cold else "warm")] = roof(ab, us)
     mask = m.boundary()
     us_ = np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1]) * np.sin(np.pi * X[:, 2])
-    g = torch.from_numpy(us_).to(dev, td)
-    b = (M * torch.from_numpy(3 * np.pi ** 2 * us_).to(dev, td)).contiguous()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    u, rep = dgo.pcg(m, 0.0, M, 1.0, K, b, mask=mask, g=g, rtol=1e-8, max_iter=5000,
-                     check_every=16, stall_iters=50 if args.dtype == "f32" else 0)
-    torch.cuda.synchronize()
-    ent["dirichlet_pcg"] = {"ms": (time.perf_counter() - t0) * 1e3, "iters": rep["iters"][0],
-                            "true_relres": rep["true_relres"][0],
-                            "nodal_err_vs_exact": float((u - g).abs().max())}
-    out["cube64_tet"] = ent
-    del m, K, M, Xd
+    for dt in (args.dtype, "f32" if args.dtype == "f64" else "f64"):
+        log(args, f"suite: Kuhn cube 64^3 {dt}")
+        tdd, ss = (torch.float64, 8) if dt == "f64" else (torch.float32, 4)
+        Xd = torch.from_numpy(X).to(dev, tdd)
+        K, M = dgo.assemble(m, Xd)
+        ent = {"dtype": dt, "nV": m.nV, "nT": m.n_elem, "nnz": m.nnz}
+        ab = alg_bytes("assemble_tet", ss, m.nV, m.n_elem, m.nnz, 1)
+        for cold in (False, True):
+            us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xd, out=(K, M)), "assemble_tet",
+                             reps, flush if cold else None)
+            ent["assemble_" + ("cold" if cold else "warm")] = roof(ab, us)
+        ent["tets_per_s_cold"] = m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
+        x1 = torch.rand(m.nV, dtype=tdd, device=dev)
+        y1 = torch.empty_like(x1)
+        ab = alg_bytes("spmm", ss, m.nV, m.n_elem, m.nnz, 1)
+        for cold in (False, True):
+            us = kernel_time(dgo, torch, lambda: dgo.spmv(m, 0.0, M, 1.0, K, x1, out=y1), "spmm",
+                             reps, flush if cold else None)
+            ent["spmv_k1_" + ("cold" if cold else "warm")] = roof(ab, us)
+        g = torch.from_numpy(us_).to(dev, tdd)
+        b = (M * torch.from_numpy(3 * np.pi ** 2 * us_).to(dev, tdd)).contiguous()
+        times = []
+        for r in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, rep = dgo.pcg(m, 0.0, M, 1.0, K, b, mask=mask, g=g, rtol=1e-8, max_iter=5000,
+                             check_every=16, stall_iters=50 if dt == "f32" else 0)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        ent["dirichlet_pcg"] = {"ms": float(np.median(times)), "iters": rep["iters"][0],
+                                "true_relres": rep["true_relres"][0],
+                                "nodal_err_vs_exact": float((u.double() - g.double()).abs().max())}
+        out["cube64_tet" if dt == args.dtype else f"cube64_tet_{dt}"] = ent
+        del K, M, Xd
+    del m
 
     # the same generator past the last-level cache: Kuhn cubes 128^3 (2.1 M
     # vertices, 12.3 M tets) and 160^3 (4.1 M vertices, 24.1 M tets): tet
@@ -470,30 +527,34 @@ def suite(args, dgo, torch, meshgen):
                      "note": "latency-bound size (0.4 MB per SpMV): reported in microseconds"}
     del m
 
-    # differentiation batch: 256 icosphere L5 meshes, VJP of assembly
-    log(args, "suite: 256 x icosphere L5 VJP")
+    # differentiation batch: 256 icosphere L5 meshes, assembly and its VJP, in
+    # both precisions
     B = 256
     X0, F = meshgen.icosphere(5)
     m = dgo.Mesh(torch.from_numpy(F).to(dev), X0.shape[0])
     Xs = np.stack([meshgen.icosphere(5, 1e-2, sd)[0] for sd in range(B)])
-    Xb = torch.from_numpy(Xs).to(dev, td)
-    Kb, Mb = dgo.assemble(m, Xb)
-    gK = torch.randn_like(Kb)
-    gM = torch.randn_like(Mb)
-    ent = {"batch": B, "nV": m.nV, "nF": m.n_elem}
-    ab = B * alg_bytes("assemble_tri", s, m.nV, m.n_elem, m.nnz, 1)
-    abv = B * alg_bytes("assemble_vjp_tri", s, m.nV, m.n_elem, m.nnz, 1)
-    for cold in (False, True):
-        tag = "cold" if cold else "warm"
-        us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xb, out=(Kb, Mb)), "assemble_tri",
-                         reps, flush if cold else None)
-        ent["assemble_" + tag] = roof(ab, us)
-        us = kernel_time(dgo, torch, lambda: dgo.assemble_vjp(m, Xb, gK, gM), "assemble_vjp_tri",
-                         reps, flush if cold else None)
-        ent["vjp_" + tag] = roof(abv, us)
-    ent["triangles_per_s_cold"] = B * m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
-    out["diff_batch_ico5"] = ent
-    del m, Xb, Kb, Mb, gK, gM
+    for dt in (args.dtype, "f32" if args.dtype == "f64" else "f64"):
+        log(args, f"suite: 256 x icosphere L5 VJP {dt}")
+        tdd, ss = (torch.float64, 8) if dt == "f64" else (torch.float32, 4)
+        Xb = torch.from_numpy(Xs).to(dev, tdd)
+        Kb, Mb = dgo.assemble(m, Xb)
+        gK = torch.randn_like(Kb)
+        gM = torch.randn_like(Mb)
+        ent = {"dtype": dt, "batch": B, "nV": m.nV, "nF": m.n_elem}
+        ab = B * alg_bytes("assemble_tri", ss, m.nV, m.n_elem, m.nnz, 1)
+        abv = B * alg_bytes("assemble_vjp_tri", ss, m.nV, m.n_elem, m.nnz, 1)
+        for cold in (False, True):
+            tag = "cold" if cold else "warm"
+            us = kernel_time(dgo, torch, lambda: dgo.assemble(m, Xb, out=(Kb, Mb)), "assemble_tri",
+                             reps, flush if cold else None)
+            ent["assemble_" + tag] = roof(ab, us)
+            us = kernel_time(dgo, torch, lambda: dgo.assemble_vjp(m, Xb, gK, gM),
+                             "assemble_vjp_tri", reps, flush if cold else None)
+            ent["vjp_" + tag] = roof(abv, us)
+        ent["triangles_per_s_cold"] = B * m.n_elem / (ent["assemble_cold"]["us"] * 1e-6)
+        out["diff_batch_ico5" if dt == args.dtype else f"diff_batch_ico5_{dt}"] = ent
+        del Xb, Kb, Mb, gK, gM
+    del m
 
     # one differentiable implicit MCF step (Sec. 7.1) on the icosphere L7:
     # forward (assemble, b = M X, PCG on (M + tau K) u = b, 3 columns) and
@@ -682,9 +743,13 @@ def serving(args, meshgen):
     n = args.serve_requests
     log(args, "serving: closed loop (batched)")
     cap = _run_server(dgo_serve, pool, n, None, True, 1)
+    sweep = {}
+    for frac in (0.5, 0.8, 1.0):
+        r = frac * cap["req_per_s"]
+        log(args, f"serving: Poisson {r:.0f} req/s = {frac} x capacity (batched)")
+        sweep[f"{frac:.1f}x"] = _run_server(dgo_serve, pool, n, r, True, 2 + int(10 * frac))
     rate = 0.8 * cap["req_per_s"]
-    log(args, f"serving: Poisson {rate:.0f} req/s (batched)")
-    b = _run_server(dgo_serve, pool, n, rate, True, 2)
+    b = sweep["0.8x"]
     log(args, "serving: closed loop (one request at a time)")
     cap1 = _run_server(dgo_serve, pool, max(64, n // 8), None, False, 3)
     log(args, f"serving: Poisson {rate:.0f} req/s (one request at a time)")
@@ -694,6 +759,7 @@ def serving(args, meshgen):
                         "iterations on (M + 1e-3 K) u = M f",
             "payload_pool": len(pool),
             "batched_closed_loop": cap, "batched_poisson": b,
+            "batched_rate_sweep": sweep,
             "one_at_a_time_closed_loop": cap1, "one_at_a_time_poisson": one,
             "speedup_req_per_s": b["req_per_s"] / one["req_per_s"],
             "note": "one-at-a-time runs use n/8 requests of the same stream (its queue "
