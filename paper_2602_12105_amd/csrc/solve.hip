@@ -51,13 +51,12 @@ using namespace kern;
 // Rows are taken in the mesh's row order: position r holds row i = rdesc[r].x
 // whose entries start at rdesc[r].y, rlen[r] of them (one load level instead
 // of order -> row pointers).
-template <typename R, int KP>
+template <typename R, int KP, int G = (KP < 8 ? 8 : KP)>
 __global__ void __launch_bounds__(T, KP <= 16 ? 8 : 4)
 k_spmm(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
        const int32_t *__restrict__ col, int32_t nV, int64_t nnz, R alpha,
        const R *__restrict__ M, R beta, const R *__restrict__ K, int k, const R *__restrict__ x,
        R *__restrict__ y, int wide) {
-    constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = T / G;
     const int64_t bt = blockIdx.y;
     M += bt * nV;
@@ -467,13 +466,12 @@ __global__ void k_cg_values(const int32_t *__restrict__ rowptr, const int32_t *_
 // ELL: the padded rows in row order (vectors in row order, i = position,
 // dvec = D^-1 in row order); otherwise CSR rows through the row descriptors
 // (vectors in natural order).
-template <typename R, int KP, bool ELL>
+template <typename R, int KP, bool ELL, int G = (KP < 8 ? 8 : KP)>
 __global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
 k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int32_t W,
           const int32_t *__restrict__ col, int32_t nV, const R *__restrict__ v,
           const R *__restrict__ dvec, int k, const R *__restrict__ r, R *__restrict__ w,
           const CgCol *__restrict__ st, double *__restrict__ part, int wide) {
-    constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = TR / G;
     __shared__ double s_part[kMaxK];
     __shared__ double s_red[red_scratch(TR, 1)];
@@ -875,6 +873,16 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
                        alpha, M, beta, K, x, y);
         return;
     }
+    if (KP < 8 && m->max_row > 8 && m->max_row <= 16) {
+        // rows of 9 to 16 entries (tetrahedral meshes) and few columns: 16
+        // lanes per row, so that a row's entries and gathers are issued in
+        // one chunk instead of two
+        dim3 grid16(nblocks_for(ntiles(m->nV, T / 16)), (unsigned)batch);
+        auto kfn16 = k_spmm<R, KP, 16>;
+        DGO_LAUNCH_EXT("spmm", s, kfn16, grid16, dim3(T), 0u, m->rdesc, m->rlen, m->col, m->nV,
+                       m->nnz, alpha, M, beta, K, k, x, y, 0);
+        return;
+    }
     dim3 grid(nblocks_for(ntiles(m->nV, T / G)), (unsigned)batch);
     auto kfn = k_spmm<R, KP>;
     DGO_LAUNCH_EXT("spmm", s, kfn, grid, dim3(T), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
@@ -992,6 +1000,16 @@ int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R 
     if (m->ell_w) {
         const int wide = (KP == 8 || KP == 16) && k == KP && m->ell_w <= 8 && ((uintptr_t)r % 16) == 0 &&
                          ((uintptr_t)w % 16) == 0;
+        if (KP < 8 && m->ell_w == 16) {
+            // padded rows of 16 entries (tetrahedral meshes) and few columns:
+            // 16 lanes per row, the row's entries and gathers in one chunk
+            const unsigned nb16 = nblocks_for(ntiles(m->nV, TR / 16), kMaxRedBlocks);
+            auto kfn16 = k_cg_sdot<R, KP, true, 16>;
+            DGO_LAUNCH_EXT("cg_sdot", s, kfn16, dim3(nb16), dim3(TR), 0u, (const int2 *)nullptr,
+                           (const uint8_t *)nullptr, m->ell_w, (const int32_t *)m->ell_col, m->nV, v,
+                           dvec, k, r, w, st, part, 0);
+            return (int)nb16;
+        }
         auto kfn = k_cg_sdot<R, KP, true>;
         DGO_LAUNCH_EXT("cg_sdot", s, kfn, dim3(nb), dim3(TR), 0u, (const int2 *)nullptr,
                        (const uint8_t *)nullptr, m->ell_w, (const int32_t *)m->ell_col, m->nV, v, dvec,

@@ -12,7 +12,9 @@
 // gives the lexicographic (min, max) rank of each edge.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -588,11 +590,12 @@ __global__ void k_build_ell(const int32_t *order, const int32_t *pos, const int3
 // Row order for the SpMV kernels. For large meshes: breadth-first search over
 // the CSR pattern from the lowest-numbered unvisited vertex of each
 // component, neighbours in ascending column order (a deterministic function
-// of the pattern). Each XCD takes a contiguous range of positions, i.e. a band
-// of BFS levels, so the x rows its rows gather are mostly those of its own
-// band and stay in its L2; in the natural order of a subdivided mesh a
-// vertex's neighbours are spread over the whole index range. Small meshes keep
-// the natural order (their x fits every L2).
+// of the pattern), kept when it is more local than the natural order. Each
+// XCD takes a contiguous range of positions, i.e. a band of BFS levels, so
+// the x rows its rows gather are mostly those of its own band and stay in its
+// L2; in the natural order of a subdivided mesh a vertex's neighbours are
+// spread over the whole index range. Small meshes keep the natural order
+// (their x fits every L2).
 static dgo_status build_row_desc(dgo_mesh *m, hipStream_t s, bool bfs) {
     const int32_t nV = m->nV;
     m->rdesc = (int2 *)m->alloc.get(sizeof(int2) * (size_t)nV, s);
@@ -640,10 +643,34 @@ static dgo_status build_row_desc(dgo_mesh *m, hipStream_t s, bool bfs) {
                 }
             }
         }
-        m->order = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)nV, s);
-        if (!m->order) return fail(DGO_ERR_NOMEM, "mesh: row order allocation failed");
-        DGO_HIP(hipMemcpyAsync(m->order, order, sizeof(int32_t) * (size_t)nV,
-                               hipMemcpyHostToDevice, s));
+        // Keep the breadth-first order only where it is more local than the
+        // natural one: per row, the largest index distance to a neighbour
+        // (natural ids, or positions in the breadth-first order), compared
+        // at the 90th percentile over the rows. Structured numberings (grids,
+        // the Kuhn cube) are local already: a row's neighbours lie within a
+        // few lines or planes, while breadth-first fronts spread every
+        // plane over the whole index range.
+        std::vector<int32_t> pos((size_t)nV), dn((size_t)nV), db((size_t)nV);
+        for (int32_t q = 0; q < nV; ++q) pos[order[q]] = q;
+        for (int32_t v = 0; v < nV; ++v) {
+            int32_t a = 0, b = 0;
+            for (int32_t t = rp[v]; t < rp[v + 1]; ++t) {
+                const int32_t j = cl[t];
+                a = std::max(a, std::abs(j - v));
+                b = std::max(b, std::abs(pos[j] - pos[v]));
+            }
+            dn[v] = a;
+            db[v] = b;
+        }
+        const size_t p90 = (size_t)((int64_t)nV * 9 / 10);
+        std::nth_element(dn.begin(), dn.begin() + p90, dn.end());
+        std::nth_element(db.begin(), db.begin() + p90, db.end());
+        if (db[p90] < dn[p90]) {
+            m->order = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)nV, s);
+            if (!m->order) return fail(DGO_ERR_NOMEM, "mesh: row order allocation failed");
+            DGO_HIP(hipMemcpyAsync(m->order, order, sizeof(int32_t) * (size_t)nV,
+                                   hipMemcpyHostToDevice, s));
+        }
     }
     k_row_desc<<<grid_for(nV, T), T, 0, s>>>(m->order, m->rowptr, nV, m->rdesc, m->rlen);
     DGO_HIP(hipGetLastError());

@@ -81,6 +81,17 @@ def _grid_with_fan(n, m, seed):
     return np.vstack([X, Xc]), np.vstack([F, Ff]).astype(np.int32)
 
 
+def _icosphere_with_fan(level, m, seed):
+    """icosphere(level) plus one vertex above the north pole joined by m
+    triangles to m + 1 consecutive vertices (a row of m + 2 entries in a mesh
+    whose rows are swept in breadth-first order)."""
+    X, F = meshgen.icosphere(level, 1e-3, seed)
+    c = X.shape[0]
+    Xc = np.array([[0.0, 0.0, 1.5]])
+    Ff = np.array([[c, i, i + 1] for i in range(m)], np.int32)
+    return np.vstack([X, Xc]), np.vstack([F, Ff]).astype(np.int32)
+
+
 MESHES = {
     "tri1": lambda: (np.array([[0.0, 0, 0], [1, 0, 0], [0.2, 0.9, 0]]), np.array([[0, 1, 2]], np.int32)),
     "tet1": lambda: (np.array([[0.0, 0, 0], [1, 0, 0], [0.1, 1, 0], [0.2, 0.3, 1]]),
@@ -99,4 +110,5 @@ MESHES = {
     "cube64": lambda: meshgen.cube_tets(64, 0.15, 0),
     "fan40": lambda: _fan(40, 2),
     "grid130fan": lambda: _grid_with_fan(130, 30, 3),
+    "ico6fan": lambda: _icosphere_with_fan(6, 30, 3),
 }

@@ -170,7 +170,7 @@ def test_spmv_parity_breadth_first_rows(k, dtype):
     test_spmv_parity("ico7", k, dtype)
 
 
-@pytest.mark.parametrize("name", ["fan40", "grid130fan"])
+@pytest.mark.parametrize("name", ["fan40", "grid130fan", "ico6fan"])
 @pytest.mark.parametrize("k", [1, 8])
 def test_spmv_parity_long_rows(name, k):
     """Rows of more than 16 entries (a fan centre)."""
@@ -292,12 +292,12 @@ def test_pcg_k13_match_oracle(dtype, k):
     assert max(rep["true_relres"]) < 1.0
 
 
-@pytest.mark.parametrize("name", ["fan40", "grid130fan"])
+@pytest.mark.parametrize("name", ["fan40", "grid130fan", "ico6fan"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_pcg_long_rows_match_oracle(name, dtype):
     """Meshes with a row of more than 16 entries iterate over CSR rows (in
-    natural order for fan40, in breadth-first order for grid130fan) instead
-    of the padded rows the other tests use."""
+    natural order for fan40 and grid130fan, in breadth-first order for
+    ico6fan) instead of the padded rows the other tests use."""
     print(f"[pcg-long-rows] {name} {dtype}", flush=True)
     X, E, m = _mesh(name)
     td = torch.float64 if dtype == "f64" else torch.float32
@@ -363,10 +363,9 @@ def _cube_problem(n, dtype):
 
 @pytest.mark.parametrize("n", [17, 26, 64])
 def test_pcg_dirichlet_cube_f64(n):
-    """Config 3 in FP64 (n = 64 is its full size, 262,144 vertices; n = 26
-    runs the masked SpMV in breadth-first row order): the solve to rtol 1e-8
-    equals the oracle's iterate of the same count at 1e-12, and the solve to
-    1e-14 equals the oracle's tight solution at 1e-12."""
+    """Config 3 in FP64 (n = 64 is its full size, 262,144 vertices): the solve
+    to rtol 1e-8 equals the oracle's iterate of the same count at 1e-12, and
+    the solve to 1e-14 equals the oracle's tight solution at 1e-12."""
     print(f"[pcg-dirichlet] cube{n} f64", flush=True)
     m, K, M, mask, g, b = _cube_problem(n, "f64")
     rp, col = [t.cpu().numpy() for t in m.csr()]
@@ -384,6 +383,29 @@ def test_pcg_dirichlet_cube_f64(n):
     wt = assert_cols_close(ut.cpu().numpy(), uo, RTOL["f64"])
     print(f"  same-count error {w:.2e}, tight error {wt:.2e}, iterations {rep['iters']}",
           flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pcg_dirichlet_breadth_first_rows(dtype):
+    """Dirichlet elimination with rows in breadth-first order (an icosphere of
+    level 7; a polar cap of fixed vertices with values z): the masked
+    iteration against the oracle's iterate of the same count."""
+    print(f"[pcg-dirichlet] icosphere L7 cap {dtype}", flush=True)
+    X, F = meshgen.icosphere(7, 1e-3, 0)
+    m = dgo.Mesh(torch.from_numpy(F).to(DEV), X.shape[0])
+    td = torch.float64 if dtype == "f64" else torch.float32
+    K, M = dgo.assemble(m, torch.from_numpy(X).to(DEV, td))
+    mask = torch.from_numpy((X[:, 2] > 0.8).astype(np.uint8)).to(DEV)
+    g = torch.from_numpy(X[:, 2].copy()).to(DEV, td)
+    f = torch.from_numpy(meshgen.normal(9, X.shape[0])).to(DEV, td)
+    b = (M * f).contiguous()
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, mask=mask, g=g, rtol=1e-8, max_iter=2000,
+                     stall_iters=20 if dtype == "f32" else 0)
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    ref = _oracle_same_iters(rp, col, 1.0, M.double().cpu().numpy(), 1e-3,
+                             K.double().cpu().numpy(), b.double().cpu().numpy(), rep["iters"],
+                             mask=mask.cpu().numpy(), g=g.double().cpu().numpy())
+    assert_cols_close(u.double().cpu().numpy(), ref, RTOL[dtype])
 
 
 def _jacobi_condition(rp, col, alpha, Mh, beta, Kh, mask=None, steps=400, seed=3):
