@@ -35,7 +35,7 @@ PAPER_NOTE = "paper publishes no figure for this metric/workload"
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE on this
 # workload, scaled by the same counters on a plain copy of known size
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_icosphere_L7_f64.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_icosphere_L{level}_{dtype}.json")
 # the sources whose change makes a stored traffic figure stale
 KERNEL_SOURCES = ["paper_2602_12105_amd/csrc/internal.hpp",
                   "paper_2602_12105_amd/csrc/kernels.hpp",
@@ -127,7 +127,7 @@ def measured_traffic(kernel, dtype, level):
     """Counter-measured HBM bytes per launch of `kernel`, or None when no
     measurement exists for this workload or the kernel sources changed since."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILE.format(level=level, dtype=dtype)) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
