@@ -66,6 +66,9 @@ def parse():
                     help="only time the FP64 oracle on every workload (single thread per "
                          "workload, and a process pool for the batched serving and "
                          "differentiation workloads), print one JSON line and exit")
+    ap.add_argument("--sweeps-only", action="store_true",
+                    help="only the kernel sweeps on icosphere L9 and the Kuhn cube 160^3 "
+                         "(--kernel-reps launches each, warm and cold), one JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a plain elementwise copy of 256 MiB (read) into 256 MiB "
                          "(write), the reference for scaling the HBM byte counters")
@@ -147,6 +150,9 @@ def main():
         sys.exit(2)
     if args.cpu_baseline_suite:
         print(json.dumps(cpu_baseline_suite(args)), flush=True)
+        return
+    if args.sweeps_only:
+        print(json.dumps(sweeps_only(args)), flush=True)
         return
 
     import numpy as np
@@ -604,7 +610,16 @@ def suite(args, dgo, torch, meshgen):
     del m, K, M, U
 
     # size sweep past the 256 MB last-level cache: icosphere L8 and L9
-    for L in (8, 9):
+    _ico_sweep(args, dgo, torch, meshgen, dev, td, s, reps, flush, (8, 9), out)
+    del flush
+    torch.cuda.empty_cache()
+    return out
+
+
+def _ico_sweep(args, dgo, torch, meshgen, dev, td, s, reps, flush, levels, out):
+    """Triangle assembly, SpMM (k = 8), intrinsic assembly, face gradient and
+    divergence (k = 1, 3) on icospheres of the given levels, warm and cold."""
+    for L in levels:
         log(args, f"suite: icosphere L{L}")
         X, F = meshgen.icosphere(L, 1e-3, 0)
         m = dgo.Mesh(torch.from_numpy(F).to(dev), X.shape[0])
@@ -650,9 +665,24 @@ def suite(args, dgo, torch, meshgen):
                 ent["face_divergence_" + tag] = roof(abd, us)
         out[f"icosphere_L{L}"] = ent
         del m, K, M, Xd, xk, yk, Ki, Mi, Ld, u, g, y, d
-    del flush
-    torch.cuda.empty_cache()
-    return out
+        torch.cuda.empty_cache()
+
+
+def sweeps_only(args):
+    """Only the kernel sweeps past the last-level cache (icosphere L9, Kuhn
+    cube 160^3), for counter collection: one JSON line."""
+    import torch
+    import meshgen
+    import paper_2602_12105_amd as dgo
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    td, s = (torch.float64, 8) if args.dtype == "f64" else (torch.float32, 4)
+    reps = max(1, args.kernel_reps)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    out = {}
+    _ico_sweep(args, dgo, torch, meshgen, dev, td, s, reps, flush, (9,), out)
+    _cube_sweep(args, dgo, torch, meshgen, dev, td, s, reps, flush, 160, out)
+    return {"dtype": args.dtype, "kernel_reps": reps, "sweeps": out}
 
 
 def _serve_payloads(meshgen, n_pool, seed=0):
