@@ -11,12 +11,13 @@
 // f at [(c * 3 + d) * nF + f], so the face kernels touch each plane with
 // coalesced accesses. G runs one thread per face (geometry once, then the k
 // fields). D runs in two launches: one thread per face forms the three corner
-// terms A_f grad phi_j . y_f of each field (coalesced, like G), then one
-// thread per (vertex, field) adds its corners over the vertex's incidence
-// list in ascending face order. The sum has a fixed order, no atomics are
-// used, and the gather pass reads one value per incidence instead of the
-// face's whole geometry (a pull over the faces directly was measured several
-// times slower: three dependent gathers per incidence).
+// terms A_f grad phi_j . y_f of each field and stores each at its corner's
+// incidence record (the vertex's incidence list holds its faces in ascending
+// order), then one thread per (vertex, field) adds its run of consecutive
+// terms in that order. The sum has a fixed order, no atomics are used, and
+// the second pass streams the terms instead of gathering them at scattered
+// face ids (a pull over the faces directly was measured several times slower:
+// three dependent gathers per incidence).
 #include "internal.hpp"
 #include <climits>
 #include "kernels.hpp"
@@ -55,11 +56,12 @@ k_face_gradient(const int32_t *__restrict__ elem, const R *__restrict__ X, int64
     }
 }
 
-// corner terms T[(c * 3 + j) * nF + f] = A_f grad phi_j . y_f
+// corner terms T[c * 3 nF + islot[3 f + j]] = A_f grad phi_j . y_f, at the
+// incidence record of corner j of face f
 template <typename R>
 __global__ void __launch_bounds__(kFaceThreads)
 k_face_corners(const int32_t *__restrict__ elem, const R *__restrict__ X, int64_t nF, int32_t k,
-               const R *__restrict__ y, R *__restrict__ T) {
+               const int32_t *__restrict__ islot, const R *__restrict__ y, R *__restrict__ T) {
     const int64_t f = (int64_t)blockIdx.x * kFaceThreads + threadIdx.x;
     if (f >= nF) return;
     const int32_t v0 = elem[3 * f], v1 = elem[3 * f + 1], v2 = elem[3 * f + 2];
@@ -70,45 +72,45 @@ k_face_corners(const int32_t *__restrict__ elem, const R *__restrict__ X, int64_
     const V3<R> w0 = scale(cross(n, sub(x2, x1)), h);
     const V3<R> w1 = scale(cross(n, sub(x0, x2)), h);
     const V3<R> w2 = scale(cross(n, sub(x1, x0)), h);
+    const int32_t q0 = islot[3 * f], q1 = islot[3 * f + 1], q2 = islot[3 * f + 2];
     for (int32_t c = 0; c < k; ++c) {
         const R *yc = y + (int64_t)c * 3 * nF + f;
         const V3<R> yf = {yc[0], yc[nF], yc[2 * nF]};
-        R *out = T + (int64_t)c * 3 * nF + f;
-        out[0] = dot(w0, yf);
-        out[nF] = dot(w1, yf);
-        out[2 * nF] = dot(w2, yf);
+        R *out = T + (int64_t)c * 3 * nF;
+        out[q0] = dot(w0, yf);
+        out[q1] = dot(w1, yf);
+        out[q2] = dot(w2, yf);
     }
 }
 
-// tslot[q] = p * nF + element of incidence record q (p: the vertex's corner)
-__global__ void k_inc_tslot(const int32_t *__restrict__ inc_elem, const uint32_t *__restrict__ inc,
-                            int64_t n_inc, int64_t nF, int32_t *__restrict__ tslot) {
+// islot[3 f + p] = q for incidence record q of the vertex at corner p of face f
+__global__ void k_face_islot(const int32_t *__restrict__ inc_elem, const uint32_t *__restrict__ inc,
+                             int64_t n_inc, int32_t *__restrict__ islot) {
     const int64_t q = (int64_t)blockIdx.x * kFaceThreads + threadIdx.x;
     if (q >= n_inc) return;
-    tslot[q] = (int32_t)((int64_t)((inc[q] >> 24) & 3u) * nF + inc_elem[q]);
+    islot[3 * (int64_t)inc_elem[q] + ((inc[q] >> 24) & 3u)] = (int32_t)q;
 }
 
 template <typename R>
 __global__ void __launch_bounds__(kFaceThreads)
-k_vertex_gather(const int32_t *__restrict__ vtptr, const int32_t *__restrict__ tslot, int32_t nV,
-                int64_t nF, int32_t k, const R *__restrict__ T, R *__restrict__ div) {
+k_vertex_gather(const int32_t *__restrict__ vtptr, int32_t nV, int64_t n_inc, int32_t k,
+                const R *__restrict__ T, R *__restrict__ div) {
     const int64_t o = (int64_t)blockIdx.x * kFaceThreads + threadIdx.x;
     if (o >= (int64_t)nV * k) return;
     const int32_t i = (int32_t)(o / k), c = (int32_t)(o - (int64_t)i * k);
-    const R *__restrict__ Tc = T + (int64_t)c * 3 * nF;
+    const R *__restrict__ Tc = T + (int64_t)c * n_inc;
     const int32_t e = vtptr[i + 1];
     int32_t q = vtptr[i];
     R acc = 0;
-    // four incidences' loads in flight at a time, added in order
+    // four terms' loads in flight at a time, added in order
     for (; q + 4 <= e; q += 4) {
-        const int32_t s0 = tslot[q], s1 = tslot[q + 1], s2 = tslot[q + 2], s3 = tslot[q + 3];
-        const R t0 = Tc[s0], t1 = Tc[s1], t2 = Tc[s2], t3 = Tc[s3];
+        const R t0 = Tc[q], t1 = Tc[q + 1], t2 = Tc[q + 2], t3 = Tc[q + 3];
         acc += t0;
         acc += t1;
         acc += t2;
         acc += t3;
     }
-    for (; q < e; ++q) acc += Tc[tslot[q]];
+    for (; q < e; ++q) acc += Tc[q];
     div[o] = acc;
 }
 
@@ -153,15 +155,15 @@ extern "C" dgo_status dgo_face_divergence(const dgo_mesh *m, dgo_dtype dtype, co
     dgo_mesh *mm = const_cast<dgo_mesh *>(m);
     const int64_t nF = m->n_elem, n = (int64_t)m->nV * k;
     if (3 * nF > INT32_MAX) return fail(DGO_ERR_UNSUPPORTED, "dgo_face_divergence: more than 2^31 / 3 faces");
-    if (!m->inc_tslot) {
+    if (!m->face_islot) {
         DGO_TRY(mesh_inc_elem(mm, s));
-        int32_t *ts = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)(m->n_inc ? m->n_inc : 1), s);
-        if (!ts) return fail(DGO_ERR_NOMEM, "dgo_face_divergence: incidence slot allocation failed");
+        int32_t *is = (int32_t *)m->alloc.get(sizeof(int32_t) * (size_t)(m->n_inc ? m->n_inc : 1), s);
+        if (!is) return fail(DGO_ERR_NOMEM, "dgo_face_divergence: corner slot allocation failed");
         if (m->n_inc)
-            k_inc_tslot<<<grid_for(m->n_inc, kFaceThreads), kFaceThreads, 0, s>>>(m->inc_elem, m->inc,
-                                                                                m->n_inc, nF, ts);
+            k_face_islot<<<grid_for(m->n_inc, kFaceThreads), kFaceThreads, 0, s>>>(m->inc_elem, m->inc,
+                                                                                 m->n_inc, is);
         DGO_HIP(hipGetLastError());
-        mm->inc_tslot = ts;
+        mm->face_islot = is;
     }
     const size_t es = dtype == DGO_F64 ? sizeof(double) : sizeof(float);
     void *T = nullptr;
@@ -170,17 +172,19 @@ extern "C" dgo_status dgo_face_divergence(const dgo_mesh *m, dgo_dtype dtype, co
         DGO_LAUNCH("face_divergence", s, {
             if (nF)
                 k_face_corners<double><<<grid_for(nF, kFaceThreads), kFaceThreads, 0, s>>>(
-                    m->elem, (const double *)d_X, nF, k, (const double *)d_y, (double *)T);
+                    m->elem, (const double *)d_X, nF, k, m->face_islot, (const double *)d_y,
+                    (double *)T);
             k_vertex_gather<double><<<grid_for(n, kFaceThreads), kFaceThreads, 0, s>>>(
-                m->vtptr, m->inc_tslot, m->nV, nF, k, (const double *)T, (double *)d_div);
+                m->vtptr, m->nV, m->n_inc, k, (const double *)T, (double *)d_div);
         });
     else
         DGO_LAUNCH("face_divergence", s, {
             if (nF)
                 k_face_corners<float><<<grid_for(nF, kFaceThreads), kFaceThreads, 0, s>>>(
-                    m->elem, (const float *)d_X, nF, k, (const float *)d_y, (float *)T);
+                    m->elem, (const float *)d_X, nF, k, m->face_islot, (const float *)d_y,
+                    (float *)T);
             k_vertex_gather<float><<<grid_for(n, kFaceThreads), kFaceThreads, 0, s>>>(
-                m->vtptr, m->inc_tslot, m->nV, nF, k, (const float *)T, (float *)d_div);
+                m->vtptr, m->nV, m->n_inc, k, (const float *)T, (float *)d_div);
         });
     DGO_HIP(hipGetLastError());
     return DGO_OK;

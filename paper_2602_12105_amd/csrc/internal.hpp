@@ -141,9 +141,9 @@ struct dgo_mesh {
     // element of each incidence record (built on first use by the kernels
     // that need the element itself: intrinsic assembly, divergence)
     int32_t *inc_elem = nullptr;     // n_inc
-    // per incidence record of a triangle mesh: p * n_elem + element, p the
-    // vertex's local position (built on first use by the divergence)
-    int32_t *inc_tslot = nullptr;    // n_inc
+    // per corner p of triangle f, at 3 f + p: the incidence record of that
+    // corner's vertex (built on first use by the divergence)
+    int32_t *face_islot = nullptr;   // 3 x n_elem
     // conformal Laplacian topology (built on first use): per CSR slot (i, j)
     // +1 if i -> j is a boundary edge in its triangle's orientation, -1 if
     // j -> i is, else 0; offsets of each row's boundary entries

@@ -384,6 +384,35 @@ __device__ __forceinline__ void tile_range(int64_t ntiles, int64_t &t0, int64_t 
     t1 = (int64_t)(lb + 1) * ntiles / nb;
 }
 
+// The tiles of this workgroup: t0, t0 + step, ... below t1. il = 0: the
+// contiguous chunk of tile_range (step 1). il != 0: the workgroups that share
+// an XCD take turns over that XCD's contiguous range (the q-th of its n
+// workgroups takes tiles q, q + n, q + 2n, ... of the range), so they sweep
+// the range together; rows that the gathers of nearby tiles share are then
+// reused from the XCD's L2 while they are still there, where with a chunk per
+// workgroup the XCD's workgroups work far apart and each chunk's rows are
+// evicted by the others' before their reuse (ranges larger than the L2).
+struct TileSeq {
+    int64_t t0, t1, step;
+};
+
+__device__ __forceinline__ TileSeq tile_seq(int64_t ntiles, int il) {
+    TileSeq q;
+    if (!il) {
+        tile_range(ntiles, q.t0, q.t1);
+        q.step = 1;
+        return q;
+    }
+    constexpr uint32_t NX = 8;
+    const uint32_t nb = gridDim.x, per = nb / NX, rem = nb % NX;
+    const uint32_t x = blockIdx.x % NX, j = blockIdx.x / NX;
+    const uint32_t start = x * per + (x < rem ? x : rem), count = per + (x < rem ? 1u : 0u);
+    q.t0 = (int64_t)start * ntiles / nb + j;
+    q.t1 = (int64_t)(start + count) * ntiles / nb;
+    q.step = count;
+    return q;
+}
+
 // ------------------------------------------------------ fixed-order reduce
 
 // Store the workgroup's W partial sums (LDS) column-major, at

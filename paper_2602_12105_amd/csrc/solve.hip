@@ -226,15 +226,16 @@ k_spmm8_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
 }
 
 // The same pipeline for one column: a lane per entry gathers x[j], and the
-// group's eight lanes are added by the shuffle tree of k_spmm (the same
-// operations in the same order as k_spmm's row for k = 1).
-template <typename R>
+// group's G lanes are added by a shuffle tree (G = 8: the same operations in
+// the same order as k_spmm's row for k = 1; G = 16 for rows of up to 16
+// entries, tetrahedral meshes, whose entries then come in one chunk).
+template <typename R, int G = 8>
 __global__ void __launch_bounds__(TR)
 k_spmm1_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
              const int32_t *__restrict__ col, int32_t nV, int64_t nnz, R alpha,
              const R *__restrict__ M, R beta, const R *__restrict__ K, const R *__restrict__ x,
              R *__restrict__ y) {
-    constexpr int G = 8, GPB = TR / G;
+    constexpr int GPB = TR / G;
     const int64_t bt = blockIdx.y;
     M += bt * nV;
     K += bt * nnz;
@@ -289,7 +290,7 @@ k_spmm1_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
             }
             acc += aj * x[cjA];
         }
-        for (int32_t e0 = 8; e0 < lA; e0 += 8) {  // rows of more than eight entries
+        for (int32_t e0 = G; e0 < lA; e0 += G) {  // rows of more than G entries
             int32_t cj = i;
             R aj = R(0);
             if (e0 + lane < lA) {
@@ -357,7 +358,7 @@ k_cg_start(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
            R beta_k, const R *__restrict__ K, const uint8_t *__restrict__ mask, int k,
            const R *__restrict__ x0, const R *__restrict__ beff, int pos_order, R *__restrict__ xp,
            const R *__restrict__ dvec, R *__restrict__ r, R *__restrict__ p, R *__restrict__ sv,
-           double *__restrict__ part) {
+           double *__restrict__ part, int il) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = TR / G;
     __shared__ double s_part[3 * kMaxK];
@@ -366,9 +367,9 @@ k_cg_start(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     const int gbase = (threadIdx.x & 63) - lane;
     const bool out_lane = lane < k && lane < KP;
     double d[3] = {0.0, 0.0, 0.0};
-    int64_t t0, t1;
-    tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    const TileSeq ts = tile_seq(((int64_t)nV + GPB - 1) / GPB, il);
+    const int64_t t0 = ts.t0, t1 = ts.t1, st_ = ts.step;
+    for (int64_t tile = t0; tile < t1; tile += st_) {
         const int64_t pos = tile * GPB + grp;
         if (pos >= nV) continue;  // uniform over the lane group
         const int2 dd = rdesc[pos];
@@ -471,7 +472,7 @@ __global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
 k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int32_t W,
           const int32_t *__restrict__ col, int32_t nV, const R *__restrict__ v,
           const R *__restrict__ dvec, int k, const R *__restrict__ r, R *__restrict__ w,
-          const CgCol *__restrict__ st, double *__restrict__ part, int wide) {
+          const CgCol *__restrict__ st, double *__restrict__ part, int wide, int il) {
     constexpr int GPB = TR / G;
     __shared__ double s_part[kMaxK];
     __shared__ double s_red[red_scratch(TR, 1)];
@@ -490,8 +491,8 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
     const bool out_lane = lane < k && lane < KP;
     constexpr int RU = ELL && KP <= 8 ? kSpmvRows : 1;
     double dsum = 0.0;
-    int64_t t0, t1;
-    tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
+    const TileSeq ts = tile_seq(((int64_t)nV + GPB - 1) / GPB, il);
+    const int64_t t0 = ts.t0, t1 = ts.t1, st_ = ts.step;
     if constexpr (ELL && (KP == 8 || KP == 16)) {
       if (wide) {
         // k = KP = 8 or 16 columns over padded rows of at most 8 entries, r
@@ -506,12 +507,13 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
         int32_t cjn = 0;
         R ajn = R(0);
         if (t0 < t1 && t0 * GPB + grp < nV) ell_entry(col, v, W, (int32_t)(t0 * GPB + grp), lane, cjn, ajn);
-        for (int64_t tile = t0; tile < t1; ++tile) {
+        for (int64_t tile = t0; tile < t1; tile += st_) {
             const int64_t row = tile * GPB + grp;
             if (row >= nV) break;  // uniform over the lane group; later tiles are past nV too
             const int32_t cj = cjn;
             const R aj = ajn;
-            if (tile + 1 < t1 && row + GPB < nV) ell_entry(col, v, W, (int32_t)(row + GPB), lane, cjn, ajn);
+            const int64_t rown = row + st_ * GPB;
+            if (tile + st_ < t1 && rown < nV) ell_entry(col, v, W, (int32_t)rown, lane, cjn, ajn);
             const Piece<R> acc = ell_row_wide<R, KP>(cj, aj, r, lane, gbase, W);
             if (lane < LPR) {
                 const int64_t e = row * KP + q * V;
@@ -534,14 +536,14 @@ k_cg_sdot(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen, int3
         return;
       }
     }
-    for (int64_t tile = t0; tile < t1; tile += RU) {
+    for (int64_t tile = t0; tile < t1; tile += RU * st_) {
         int32_t i[RU], rb[RU], len[RU];
         bool ok[RU];
         R dt[RU], acc[RU], ri[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {  // uniform over the lane group
-            const int64_t pos = (tile + u) * GPB + grp;
-            ok[u] = tile + u < t1 && pos < nV;
+            const int64_t pos = (tile + u * st_) * GPB + grp;
+            ok[u] = tile + u * st_ < t1 && pos < nV;
             if (ELL) {
                 i[u] = ok[u] ? (int32_t)pos : 0;
                 rb[u] = i[u] * W;
@@ -808,7 +810,8 @@ __global__ void __launch_bounds__(TR, KP <= 8 ? 8 : 4)
 k_cg_trueres_rows(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
                   const int32_t *__restrict__ col, int32_t nV, R alpha_m, const R *__restrict__ M,
                   R beta_k, const R *__restrict__ K, const uint8_t *__restrict__ mask, int k,
-                  const R *__restrict__ beff, const R *__restrict__ u, double *__restrict__ part) {
+                  const R *__restrict__ beff, const R *__restrict__ u, double *__restrict__ part,
+                  int il) {
     constexpr int G = KP < 8 ? 8 : KP;
     constexpr int GPB = TR / G;
     __shared__ double s_part[kMaxK];
@@ -817,9 +820,9 @@ k_cg_trueres_rows(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rl
     const int gbase = (threadIdx.x & 63) - lane;
     const bool out_lane = lane < k && lane < KP;
     double d = 0.0;
-    int64_t t0, t1;
-    tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    const TileSeq ts = tile_seq(((int64_t)nV + GPB - 1) / GPB, il);
+    const int64_t t0 = ts.t0, t1 = ts.t1, st_ = ts.step;
+    for (int64_t tile = t0; tile < t1; tile += st_) {
         const int64_t pos = tile * GPB + grp;
         if (pos >= nV) continue;  // uniform over the lane group
         const int2 dd = rdesc[pos];
@@ -842,6 +845,20 @@ unsigned nblocks_for(int64_t ntiles, int64_t cap = kMaxBlocks) {
 }
 
 int64_t ntiles(int64_t nV, int rows_per_tile) { return (nV + rows_per_tile - 1) / rows_per_tile; }
+
+// Tile order of the PCG kernels that gather (tile_seq): interleaved over each
+// XCD's workgroups once the gathered vector of one XCD's share of the rows is
+// larger than half its 4 MB L2, else a contiguous chunk per workgroup. These
+// grids hold one or two workgroups per CU with many tiles each (w = A z at
+// the icosphere L9, 8 FP64 columns: 186 -> 172 us per iteration). The SpMM
+// grids are not persistent (workgroups of about five tiles, dispatched in
+// order), so their resident workgroups already work on neighbouring chunks;
+// interleaving them was slower (L9, 8 columns: 201 -> 210 us).
+constexpr int64_t kXcdL2Bytes = 4 << 20;
+
+int gather_il(const dgo_mesh *m, int k, size_t es) {
+    return (int64_t)m->nV * k * (int64_t)es / 8 > kXcdL2Bytes / 2 ? 1 : 0;
+}
 
 // ------------------------------------------------------------- dispatch
 
@@ -869,6 +886,14 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
         const int64_t nt1 = ntiles(m->nV, TR / 8);
         dim3 grid1(nblocks_for(nt1, std::max<int64_t>(256, nt1 / 5)), (unsigned)batch);
         auto kfn1 = k_spmm1_pipe<R>;
+        DGO_LAUNCH_EXT("spmm", s, kfn1, grid1, dim3(TR), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
+                       alpha, M, beta, K, x, y);
+        return;
+    }
+    if (KP == 1 && m->max_row <= 16) {  // one column, rows of 9 to 16 entries: 16 lanes per row
+        const int64_t nt1 = ntiles(m->nV, TR / 16);
+        dim3 grid1(nblocks_for(nt1, std::max<int64_t>(256, nt1 / 5)), (unsigned)batch);
+        auto kfn1 = k_spmm1_pipe<R, 16>;
         DGO_LAUNCH_EXT("spmm", s, kfn1, grid1, dim3(TR), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
                        alpha, M, beta, K, x, y);
         return;
@@ -913,7 +938,8 @@ int launch_cg_start_kp(const dgo_mesh *m, R alpha, const R *M, R beta, const R *
     DGO_LAUNCH("cg_start", s,
                k_cg_start<R, KP, MASK><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV, alpha, M,
                                                         beta, K, mask, k, x0, beff, pos_order, xp,
-                                                        dvec, r, p, sv, part));
+                                                        dvec, r, p, sv, part,
+                                                        gather_il(m, k, sizeof(R))));
     return (int)nb;
 }
 
@@ -957,7 +983,7 @@ int launch_trueres_rows_kp(const dgo_mesh *m, R alpha, const R *M, R beta, const
     DGO_LAUNCH("cg_trueres", s,
                k_cg_trueres_rows<R, KP, MASK><<<nb, TR, 0, s>>>(m->rdesc, m->rlen, m->col, m->nV,
                                                                alpha, M, beta, K, mask, k, beff, u,
-                                                               part));
+                                                               part, gather_il(m, k, sizeof(R))));
     return (int)nb;
 }
 
@@ -997,6 +1023,7 @@ int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R 
                    const CgCol *st, double *part, hipStream_t s) {
     constexpr int G = KP < 8 ? 8 : KP;
     const unsigned nb = nblocks_for(ntiles(m->nV, TR / G), KP >= 8 ? kSdotBlocks : kMaxRedBlocks);
+    const int il = gather_il(m, k, sizeof(R));
     if (m->ell_w) {
         const int wide = (KP == 8 || KP == 16) && k == KP && m->ell_w <= 8 && ((uintptr_t)r % 16) == 0 &&
                          ((uintptr_t)w % 16) == 0;
@@ -1007,18 +1034,18 @@ int launch_sdot_kp(const dgo_mesh *m, const R *v, const R *dvec, int k, const R 
             auto kfn16 = k_cg_sdot<R, KP, true, 16>;
             DGO_LAUNCH_EXT("cg_sdot", s, kfn16, dim3(nb16), dim3(TR), 0u, (const int2 *)nullptr,
                            (const uint8_t *)nullptr, m->ell_w, (const int32_t *)m->ell_col, m->nV, v,
-                           dvec, k, r, w, st, part, 0);
+                           dvec, k, r, w, st, part, 0, il);
             return (int)nb16;
         }
         auto kfn = k_cg_sdot<R, KP, true>;
         DGO_LAUNCH_EXT("cg_sdot", s, kfn, dim3(nb), dim3(TR), 0u, (const int2 *)nullptr,
                        (const uint8_t *)nullptr, m->ell_w, (const int32_t *)m->ell_col, m->nV, v, dvec,
-                       k, r, w, st, part, wide);
+                       k, r, w, st, part, wide, il);
     } else {
         auto kfn = k_cg_sdot<R, KP, false>;
         DGO_LAUNCH_EXT("cg_sdot", s, kfn, dim3(nb), dim3(TR), 0u, (const int2 *)m->rdesc,
                        (const uint8_t *)m->rlen, 0, (const int32_t *)m->col, m->nV, v, dvec, k, r, w,
-                       st, part, 0);
+                       st, part, 0, il);
     }
     return (int)nb;
 }

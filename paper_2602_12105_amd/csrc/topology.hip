@@ -705,7 +705,7 @@ static void release(dgo_mesh *m, hipStream_t s) {
     void *ptrs[] = {m->elem, m->EV, m->elem_edge, m->elem_sign, m->rowptr, m->col,
                     m->diag, m->vtptr, m->inc, m->bmask, m->rdesc, m->rlen, m->order,
                     m->ell_col, m->ell_src, m->vjp_mirror, m->vjp_coldiag, m->vjp_opp,
-                    m->inc_elem, m->inc_tslot, m->conf_bslot, m->conf_bptr, m->ws};
+                    m->inc_elem, m->face_islot, m->conf_bslot, m->conf_bptr, m->ws};
     for (void *p : ptrs) m->alloc.put(p, s);
 }
 
