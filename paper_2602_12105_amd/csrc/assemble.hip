@@ -6,8 +6,10 @@
 // accumulating each element's contribution to the row's off-diagonal slots in
 // LDS. A workgroup owns a contiguous block of rows, so its slots form one
 // contiguous span of Kvals: the span's column ids are staged in LDS on the way
-// in and the finished values leave with coalesced stores. No float atomics are
-// used: every sum has a fixed order and the output is bitwise deterministic.
+// in and the finished values leave with coalesced stores. No two threads add
+// into one value: every sum has a fixed order and the output is bitwise
+// deterministic (the FP64 row sums use LDS add instructions, each slot only
+// by the thread of its row, in that thread's order).
 //
 // Bitwise symmetry: the weight of edge ij is summed in row i and in row j over
 // the same elements in the same order, and each element term is evaluated from

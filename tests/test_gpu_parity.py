@@ -177,9 +177,17 @@ def test_spmv_parity_long_rows(name, k):
     test_spmv_parity(name, k, "f64")
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmv_parity_tet_rows_full_size(dtype):
+    """One column on the Kuhn cube 64^3 (rows of up to 15 entries, 16 lanes
+    per row in the one-column pipeline), at the size of the Dirichlet workload."""
+    test_spmv_parity("cube64", 1, dtype)
+
+
+@pytest.mark.parametrize("name", ["ico3", "cube9"])
 @pytest.mark.parametrize("k", [1, 4, 8])
-def test_spmv_batch(k):
-    X, E, m = _mesh("ico3")
+def test_spmv_batch(name, k):
+    X, E, m = _mesh(name)
     Xb = torch.from_numpy(np.stack([X, 1.1 * X])).to(DEV)
     K, M = dgo.assemble(m, Xb)
     x = torch.from_numpy(meshgen.normal(3, 2 * X.shape[0] * k).reshape(2, -1, k)).to(DEV)
