@@ -312,24 +312,25 @@ template <typename R>
 dgo_status launch_assemble(const dgo_mesh *m, int32_t batch, const void *X,
                            const dgo_assemble_opts *o, void *K, void *M, int32_t *ndeg,
                            hipStream_t s) {
-    const size_t lds = (size_t)assembly_lds_bytes(m->dim, (int)sizeof(R), m->rpb, m->max_block_nnz,
-                                                  m->max_block_inc);
-    dim3 grid((unsigned)m->nblocks, (unsigned)batch);
+    const bool f32 = sizeof(R) == 4;
+    const AsmView v = f32 ? view_of_f32(m) : view_of(m);
+    const int32_t nblocks = f32 ? m->nblocks_f32 : m->nblocks;
+    const size_t lds = (size_t)assembly_lds_bytes(m->dim, (int)sizeof(R), v.rpb, v.span_max,
+                                                  v.inc_max);
+    dim3 grid((unsigned)nblocks, (unsigned)batch);
     const int uc = o && o->use_clamp ? 1 : 0;
     const R cm = o ? (R)o->clamp_min : R(0);
     const int mk = o ? o->mass : 0;
     if (m->dim == 2)
     {
         auto kfn = k_assemble<R, 2>;
-        DGO_LAUNCH_EXT("assemble_tri", s, kfn, grid, dim3(kAssembleThreads), (uint32_t)lds,
-                       view_of(m), m->nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg,
-                       mk);
+        DGO_LAUNCH_EXT("assemble_tri", s, kfn, grid, dim3(kAssembleThreads), (uint32_t)lds, v,
+                       nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg, mk);
     }
     else
         DGO_LAUNCH("assemble_tet", s,
                    k_assemble<R, 3><<<grid, kAssembleThreads, lds, s>>>(
-                       view_of(m), m->nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg,
-                       0));
+                       v, nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg, 0));
     DGO_HIP(hipGetLastError());
     return DGO_OK;
 }

@@ -155,6 +155,10 @@ struct dgo_mesh {
     int32_t nblocks = 0;        // ceil(nV / rpb)
     int32_t max_block_nnz = 0;  // largest CSR span of one block of rows
     int32_t max_block_inc = 0;  // most incidence records of one block of rows
+    // the row blocks of FP32 assembly (tetrahedral meshes: twice the rows of
+    // the FP64 blocks, whose LDS the FP32 terms halve; triangle meshes: the
+    // same blocks as FP64)
+    int32_t rpb_f32 = 0, nblocks_f32 = 0, max_block_nnz_f32 = 0, max_block_inc_f32 = 0;
     int64_t lds_budget = 0;     // LDS bytes a row block may take (0: kRowBlockLdsBytes)
 
     // scratch workspace reused by numeric calls (grows on demand)
@@ -221,7 +225,11 @@ dgo_status exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *t
 // block's CSR span (values and column ids), one record and CW contributions
 // per incidence, and the block's row and incidence offsets.
 constexpr int32_t kRowsPerBlockTri = 64;
+// tets: 16 rows per block in FP64 (32 rows: 4 instead of 8 resident blocks per
+// CU, 1.40 -> 1.60 ms at the Kuhn cube 160^3), 32 in FP32 (still 8 per CU, and
+// phase B on 32 lanes: 1.30 -> 0.84 ms; 64 rows: 1.11 ms)
 constexpr int32_t kRowsPerBlockTet = 16;
+constexpr int32_t kRowsPerBlockTetF32 = 32;
 constexpr int64_t kRowBlockLdsBytes = 64 * 1024;
 constexpr int kAssembleThreads = 256;
 

@@ -906,4 +906,10 @@ inline kern::AsmView view_of(const dgo_mesh *m) {
     return {m->rowptr, m->col, m->vtptr, m->inc, m->nV, m->rpb, m->max_block_nnz, m->max_block_inc};
 }
 
+// The row blocks of FP32 assembly (m->rpb_f32 and its sizes).
+inline kern::AsmView view_of_f32(const dgo_mesh *m) {
+    return {m->rowptr, m->col, m->vtptr, m->inc, m->nV, m->rpb_f32, m->max_block_nnz_f32,
+            m->max_block_inc_f32};
+}
+
 }  // namespace dgo

@@ -547,6 +547,30 @@ static dgo_status build(dgo_mesh *m, const int32_t *d_elem, hipStream_t s) {
         return fail(DGO_ERR_UNSUPPORTED, "mesh: a vertex has more than 254 neighbours");
     if (assembly_lds_bytes(dim, 8, rpb, hf[5], hf[6]) > budget)
         return fail(DGO_ERR_UNSUPPORTED, "mesh: a vertex's row exceeds the LDS budget");
+    m->rpb_f32 = m->rpb;
+    m->nblocks_f32 = m->nblocks;
+    m->max_block_nnz_f32 = m->max_block_nnz;
+    m->max_block_inc_f32 = m->max_block_inc;
+    if (dim == 3 && nV) {
+        // FP32 blocks of tetrahedral meshes: the most rows up to
+        // kRowsPerBlockTetF32 whose FP32 LDS fits the budget (never fewer than
+        // the FP64 blocks, which fit it with FP64 terms)
+        for (int32_t r32 = kRowsPerBlockTetF32; r32 > m->rpb; r32 /= 2) {
+            DGO_HIP(hipMemsetAsync(flags + 5, 0, 2 * sizeof(int32_t), s));
+            const int32_t nb = (int32_t)((nV + r32 - 1) / r32);
+            k_block_nnz<<<grid_for(nb, T), T, 0, s>>>(m->rowptr, m->vtptr, nV, r32, flags + 5);
+            DGO_HIP(hipGetLastError());
+            DGO_HIP(hipMemcpyAsync(hf + 5, flags + 5, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            DGO_HIP(hipStreamSynchronize(s));
+            if (assembly_lds_bytes(dim, 4, r32, hf[5], hf[6]) <= budget) {
+                m->rpb_f32 = r32;
+                m->nblocks_f32 = nb;
+                m->max_block_nnz_f32 = hf[5];
+                m->max_block_inc_f32 = hf[6];
+                break;
+            }
+        }
+    }
     return DGO_OK;
 }
 
