@@ -54,26 +54,55 @@ k_assemble_intrinsic(AsmView v, int32_t nblocks, int64_t nnz, int64_t nE,
 
 // ------------------------------------------------------------------- VJP
 
+// A triangle (i, a, b)'s contribution to d loss / d x_i: gia, gib, gab are the
+// loss gradients of the half-cotangent weights of edges ia, ib, ab (each half
+// cot the cot of the angle opposite the edge, at b, a and i), gm the summed
+// lumped-mass gradients of the three vertices (their mass is area / 3). The
+// corners' derivatives share the triangle's s = |e_ia x e_ib| (twice its
+// area, the same at every corner) and its edge vectors e_ia = x_a - x_i,
+// e_ib = x_b - x_i, e_ab = x_b - x_a. The cot of the angle between edges e1
+// and e2 of a corner is d / s with d = e1.e2, and d cot / d e1 =
+// e2 / s - d (|e2|^2 e1 - d e2) / s^3 (symmetrically for e2). With d the
+// corner's dot product and l the squared lengths:
+//   corner b (e1 = -e_ib, e2 = -e_ab, d/dx_i = d/de1):
+//     -e_ab / s - d_b (-l_ab e_ib + d_b e_ab) / s^3
+//   corner a (e1 = -e_ia, e2 = e_ab):
+//      e_ab / s - d_a (-l_ab e_ia - d_a e_ab) / s^3
+//   corner i (e1 = e_ia, e2 = e_ib, d/dx_i = -(d/de1 + d/de2)):
+//     -[(e_ia + e_ib) / s - d_i W / s^3],  W = (l_ib - d_i) e_ia + (l_ia - d_i) e_ib
+//   area: d(s/2)/dx_i = -W / (2 s).
 template <typename R>
-struct CotD {  // d cot / d e1 and d cot / d e2
-    V3<R> d1, d2;
-};
-
-// cot of the angle between e1 and e2 differentiated: with d = e1.e2,
-// s = |e1 x e2|: d cot/d e1 = e2/s - d (|e2|^2 e1 - d e2)/s^3, and
-// symmetrically for e2.
-template <typename R>
-__device__ __forceinline__ CotD<R> cot_diff(V3<R> e1, V3<R> e2) {
-    const V3<R> n = cross(e1, e2);
-    const R s = sqrt(dot(n, n));
-    const R d = dot(e1, e2), l1 = dot(e1, e1), l2 = dot(e2, e2);
-    const R is = R(1) / s, ds3 = d * is * is * is;
-    CotD<R> r;
-    r.d1 = {e2.x * is - ds3 * (l2 * e1.x - d * e2.x), e2.y * is - ds3 * (l2 * e1.y - d * e2.y),
-            e2.z * is - ds3 * (l2 * e1.z - d * e2.z)};
-    r.d2 = {e1.x * is - ds3 * (l1 * e2.x - d * e1.x), e1.y * is - ds3 * (l1 * e2.y - d * e1.y),
-            e1.z * is - ds3 * (l1 * e2.z - d * e1.z)};
-    return r;
+__device__ __forceinline__ V3<R> vjp_corner(V3<R> xi, V3<R> xa, V3<R> xb, R gia, R gib, R gab,
+                                            R gm, bool has_k, bool has_m) {
+    const V3<R> eia = sub(xa, xi), eib = sub(xb, xi), eab = sub(xb, xa);
+    const V3<R> n = cross(eia, eib);
+    const R sn = sqrt(dot(n, n));
+    const R is = R(1) / sn, is3 = is * is * is;
+    const R lia = dot(eia, eia), lib = dot(eib, eib), lab = dot(eab, eab);
+    const R di = dot(eia, eib);
+    const V3<R> W = axpy(lib - di, eia, V3<R>{(lia - di) * eib.x, (lia - di) * eib.y,
+                                              (lia - di) * eib.z});
+    V3<R> g = {R(0), R(0), R(0)};
+    if (has_k) {
+        const R db = dot(eib, eab), da = -dot(eia, eab);
+        // 1/2 cot(at b) on edge ia
+        const R cb1 = R(0.5) * gia * is, cb3 = R(0.5) * gia * db * is3;
+        // 1/2 cot(at a) on edge ib
+        const R ca1 = R(0.5) * gib * is, ca3 = R(0.5) * gib * da * is3;
+        // 1/2 cot(at i) on edge ab
+        const R ci1 = R(-0.5) * gab * is, ci3 = R(-0.5) * gab * di * is3;
+        g.x = -cb1 * eab.x - cb3 * (db * eab.x - lab * eib.x) + ca1 * eab.x +
+              ca3 * (lab * eia.x + da * eab.x) + ci1 * (eia.x + eib.x) - ci3 * W.x;
+        g.y = -cb1 * eab.y - cb3 * (db * eab.y - lab * eib.y) + ca1 * eab.y +
+              ca3 * (lab * eia.y + da * eab.y) + ci1 * (eia.y + eib.y) - ci3 * W.y;
+        g.z = -cb1 * eab.z - cb3 * (db * eab.z - lab * eib.z) + ca1 * eab.z +
+              ca3 * (lab * eia.z + da * eab.z) + ci1 * (eia.z + eib.z) - ci3 * W.z;
+    }
+    if (has_m) {
+        const R ga = -(gm / R(3)) * (R(0.5) * is);
+        g = axpy(ga, W, g);
+    }
+    return g;
 }
 
 __device__ __forceinline__ int32_t find_slot(const int32_t *__restrict__ rowptr,
@@ -119,30 +148,9 @@ k_assemble_vjp_tri(const int32_t *__restrict__ rowptr, const int32_t *__restrict
             gib = -gK[sib] - gK[find_slot(rowptr, col, b, i)] + gKii + gKbb;
             gab = -gK[find_slot(rowptr, col, a, b)] - gK[find_slot(rowptr, col, b, a)] + gKaa + gKbb;
         }
-        // 1/2 cot(at b) on edge ia: e1 = xi - xb, e2 = xa - xb; d/dxi = d/de1
-        const CotD<R> cb = cot_diff(sub(xi, xb), sub(xa, xb));
-        g = axpy(R(0.5) * gia, cb.d1, g);
-        // 1/2 cot(at a) on edge ib: e1 = xi - xa, e2 = xb - xa
-        const CotD<R> ca = cot_diff(sub(xi, xa), sub(xb, xa));
-        g = axpy(R(0.5) * gib, ca.d1, g);
-        // 1/2 cot(at i) on edge ab: e1 = xa - xi, e2 = xb - xi; d/dxi = -(d1 + d2)
-        const CotD<R> ci = cot_diff(sub(xa, xi), sub(xb, xi));
-        const R hi = R(-0.5) * gab;
-        g = axpy(hi, ci.d1, g);
-        g = axpy(hi, ci.d2, g);
-        if (gM) {
-            // area = |e1 x e2|/2 with e1 = xa - xi, e2 = xb - xi:
-            // d area/dxi = -[(|e2|^2 e1 - d e2) + (|e1|^2 e2 - d e1)] / (2 s)
-            const V3<R> e1 = sub(xa, xi), e2 = sub(xb, xi);
-            const V3<R> n = cross(e1, e2);
-            const R s = sqrt(dot(n, n));
-            const R d = dot(e1, e2), l1 = dot(e1, e1), l2 = dot(e2, e2);
-            const R ga = -(gMi + gM[a] + gM[b]) / R(3) / (R(2) * s);
-            g = axpy(ga, V3<R>{l2 * e1.x - d * e2.x + l1 * e2.x - d * e1.x,
-                               l2 * e1.y - d * e2.y + l1 * e2.y - d * e1.y,
-                               l2 * e1.z - d * e2.z + l1 * e2.z - d * e1.z},
-                     g);
-        }
+        const R gm = gM ? gMi + gM[a] + gM[b] : R(0);
+        const V3<R> t = vjp_corner(xi, xa, xb, gia, gib, gab, gm, gK != nullptr, gM != nullptr);
+        g = {g.x + t.x, g.y + t.y, g.z + t.z};
     }
     gX[3 * (int64_t)i + 0] = g.x;
     gX[3 * (int64_t)i + 1] = g.y;
@@ -263,30 +271,8 @@ k_vjp_rows(AsmView v, const int32_t *__restrict__ diag, const int32_t *__restric
             gib = lgii[rr] + lgd[lb] - lsum[lb];
             gab = lgd[la] + lgd[lb] - gK[lopp[q]] - gK[lopp[inc_max + q]];
         }
-        V3<R> g = {R(0), R(0), R(0)};
-        // 1/2 cot(at b) on edge ia: e1 = xi - xb, e2 = xa - xb; d/dxi = d/de1
-        const CotD<R> cb = cot_diff(sub(xi, xb), sub(xa, xb));
-        g = axpy(R(0.5) * gia, cb.d1, g);
-        // 1/2 cot(at a) on edge ib: e1 = xi - xa, e2 = xb - xa
-        const CotD<R> ca = cot_diff(sub(xi, xa), sub(xb, xa));
-        g = axpy(R(0.5) * gib, ca.d1, g);
-        // 1/2 cot(at i) on edge ab: e1 = xa - xi, e2 = xb - xi; d/dxi = -(d1 + d2)
-        const CotD<R> ci = cot_diff(sub(xa, xi), sub(xb, xi));
-        const R hi = R(-0.5) * gab;
-        g = axpy(hi, ci.d1, g);
-        g = axpy(hi, ci.d2, g);
-        if (gM) {
-            // d area/dxi = -[(|e2|^2 e1 - d e2) + (|e1|^2 e2 - d e1)] / (2 s)
-            const V3<R> e1 = sub(xa, xi), e2 = sub(xb, xi);
-            const V3<R> n = cross(e1, e2);
-            const R sn = sqrt(dot(n, n));
-            const R d = dot(e1, e2), l1 = dot(e1, e1), l2 = dot(e2, e2);
-            const R ga = -(lgmi[rr] + lgm[la] + lgm[lb]) / R(3) / (R(2) * sn);
-            g = axpy(ga, V3<R>{l2 * e1.x - d * e2.x + l1 * e2.x - d * e1.x,
-                               l2 * e1.y - d * e2.y + l1 * e2.y - d * e1.y,
-                               l2 * e1.z - d * e2.z + l1 * e2.z - d * e1.z},
-                     g);
-        }
+        const R gm = gM ? lgmi[rr] + lgm[la] + lgm[lb] : R(0);
+        const V3<R> g = vjp_corner(xi, xa, xb, gia, gib, gab, gm, gK != nullptr, gM != nullptr);
         cw[q] = g.x;
         cw[inc_max + q] = g.y;
         cw[2 * (size_t)inc_max + q] = g.z;

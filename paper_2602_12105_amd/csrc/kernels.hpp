@@ -245,6 +245,14 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
     const int32_t s0 = rowptr[r0], span = rowptr[r1] - s0;
     const int32_t q0 = vtptr[r0], ninc = vtptr[r1] - q0;
     const int t = threadIdx.x;
+    // intrinsic: the triangles of this thread's first two incidences are
+    // loaded with the staging (they head phase A's chain of dependent loads:
+    // triangle, its edges, their lengths)
+    int32_t fpre0 = 0, fpre1 = 0;
+    if constexpr (INTR) {
+        if (t < ninc) fpre0 = inc_elem[q0 + t];
+        if (t + (int32_t)blockDim.x < ninc) fpre1 = inc_elem[q0 + t + blockDim.x];
+    }
     for (int32_t j = t; j <= nrows; j += blockDim.x) {
         L.lrp[j] = rowptr[r0 + j] - s0;
         L.lvt[j] = vtptr[r0 + j] - q0;
@@ -258,7 +266,8 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
     __syncthreads();
     int ndeg = 0;
     // phase A: element terms per incidence, from LDS only
-    for (int32_t q = t; q < ninc; q += blockDim.x) {
+    int32_t it = 0;  // this thread's pass over the block's incidences
+    for (int32_t q = t; q < ninc; q += blockDim.x, ++it) {
         const uint32_t rec = L.lrec[q];
         const int32_t rr = rec_row(rec, rpb);
         const int32_t i = r0 + rr, base = L.lrp[rr];
@@ -267,7 +276,14 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             // triangle (i, a, b) in cyclic order; edge ids by the rule that
             // slot j of a triangle is the edge opposite its vertex j
             const int p = (int)((rec >> 24) & 3u);
-            const int32_t *fe = elem_edge + 3 * (int64_t)inc_elem[q0 + q];
+            int32_t f;
+            if (it == 0)
+                f = fpre0;
+            else if (it == 1)
+                f = fpre1;
+            else
+                f = inc_elem[q0 + q];
+            const int32_t *fe = elem_edge + 3 * (int64_t)f;
             const int pa = p == 2 ? 0 : p + 1, pb = p == 0 ? 2 : p - 1;
             const R ei = X[fe[p]], ea = X[fe[pa]], eb = X[fe[pb]];  // opposite i, a, b
             R A;
