@@ -121,11 +121,11 @@ __device__ __forceinline__ V3<R> sel2v(bool c, V3<R> a, V3<R> b) {
     return {c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
 }
 
-// LDS layout of the assembly kernels for one block of rows [r0, r1). Arrays
-// of records are stored field-major (structure of arrays) so that lanes
-// touching consecutive entries hit consecutive banks:
+// LDS layout of the assembly kernels for one block of rows [r0, r1):
+//   cw   : R[inc_max][CW]   per-incidence contributions (phase A), an
+//                           incidence's CW terms side by side, so that phase B
+//                           reads them from one address (16-byte aligned: first)
 //   acc  : R[span]          the block's CSR values (accumulated, then finished)
-//   cw   : R[CW][inc_max]   per-incidence contributions (phase A)
 //   lcol : int32[span]      the block's column ids
 //   lrec : uint32[ninc]     the block's incidence records
 //   lrp  : int32[rpb + 1]   row offsets into the span
@@ -142,14 +142,14 @@ struct BlockLds {
     int32_t inc_max, span_max, rpb;
     __device__ BlockLds(unsigned char *smem, int32_t span_max_, int32_t inc_max_, int32_t rpb_)
         : inc_max(inc_max_), span_max(span_max_), rpb(rpb_) {
-        acc = (R *)smem;
-        cw = acc + span_max;
-        lcol = (int32_t *)(cw + (size_t)inc_max * CW);
+        cw = (R *)smem;
+        acc = cw + (size_t)inc_max * CW;
+        lcol = (int32_t *)(acc + span_max);
         lrec = (uint32_t *)(lcol + span_max);
         lrp = (int32_t *)(lrec + inc_max);
         lvt = lrp + rpb + 1;
     }
-    __device__ R &c(int f, int32_t q) { return cw[(size_t)f * inc_max + q]; }
+    __device__ R &c(int f, int32_t q) { return cw[(size_t)q * CW + f]; }
 };
 
 // Row of an incidence record within its block: the record carries its
@@ -362,22 +362,27 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
     for (int32_t rr = t; rr < nrows; rr += blockDim.x) {
         const int32_t base = L.lrp[rr], len = L.lrp[rr + 1] - base, i = r0 + rr;
         R m = 0;
-        for (int32_t q = L.lvt[rr]; q < L.lvt[rr + 1]; ++q) {
+        const int32_t qe = L.lvt[rr + 1];
+        for (int32_t q = L.lvt[rr]; q < qe; ++q) {
             const uint32_t rec = L.lrec[q];
+            // the incidence's terms are read before any add into the row's
+            // slots, so that the reads go out together
+            const R *cq = L.cw + (size_t)q * CW;
+            const R c0 = cq[0], c1 = cq[1], c2 = cq[2], cm = cq[CW - 1];
             if constexpr (sizeof(R) == 8) {
                 // FP64: LDS adds without return (one LDS round trip per
                 // incidence instead of two; each slot belongs to this thread
                 // alone, so its adds run in this order; tets 1472 -> 1404 us
                 // at the Kuhn cube 160^3). The FP32 form was measured slower.
-                atomicAdd(&L.acc[base + (rec & 255u)], L.c(0, q));
-                atomicAdd(&L.acc[base + ((rec >> 8) & 255u)], L.c(1, q));
-                if (DIM == 3) atomicAdd(&L.acc[base + ((rec >> 16) & 255u)], L.c(2, q));
+                atomicAdd(&L.acc[base + (rec & 255u)], c0);
+                atomicAdd(&L.acc[base + ((rec >> 8) & 255u)], c1);
+                if (DIM == 3) atomicAdd(&L.acc[base + ((rec >> 16) & 255u)], c2);
             } else {
-                L.acc[base + (rec & 255u)] += L.c(0, q);
-                L.acc[base + ((rec >> 8) & 255u)] += L.c(1, q);
-                if (DIM == 3) L.acc[base + ((rec >> 16) & 255u)] += L.c(2, q);
+                L.acc[base + (rec & 255u)] += c0;
+                L.acc[base + ((rec >> 8) & 255u)] += c1;
+                if (DIM == 3) L.acc[base + ((rec >> 16) & 255u)] += c2;
             }
-            m += L.c(CW - 1, q);
+            m += cm;
         }
         R sum = 0;
         int32_t dslot = 0;
