@@ -363,7 +363,26 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
         const int32_t base = L.lrp[rr], len = L.lrp[rr + 1] - base, i = r0 + rr;
         R m = 0;
         const int32_t qe = L.lvt[rr + 1];
-        for (int32_t q = L.lvt[rr]; q < qe; ++q) {
+        int32_t q = L.lvt[rr];
+        if constexpr (sizeof(R) == 8) {
+            // FP64, two incidences at a time: both incidences' terms are read
+            // before their adds (which read nothing back), in incidence order
+            for (; q + 1 < qe; q += 2) {
+                const uint32_t ra = L.lrec[q], rb = L.lrec[q + 1];
+                const R *ca = L.cw + (size_t)q * CW, *cb = ca + CW;
+                const R a0 = ca[0], a1 = ca[1], a2 = ca[2], am = ca[CW - 1];
+                const R b0 = cb[0], b1 = cb[1], b2 = cb[2], bm = cb[CW - 1];
+                atomicAdd(&L.acc[base + (ra & 255u)], a0);
+                atomicAdd(&L.acc[base + ((ra >> 8) & 255u)], a1);
+                if (DIM == 3) atomicAdd(&L.acc[base + ((ra >> 16) & 255u)], a2);
+                atomicAdd(&L.acc[base + (rb & 255u)], b0);
+                atomicAdd(&L.acc[base + ((rb >> 8) & 255u)], b1);
+                if (DIM == 3) atomicAdd(&L.acc[base + ((rb >> 16) & 255u)], b2);
+                m += am;
+                m += bm;
+            }
+        }
+        for (; q < qe; ++q) {
             const uint32_t rec = L.lrec[q];
             // the incidence's terms are read before any add into the row's
             // slots, so that the reads go out together
@@ -384,16 +403,31 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             }
             m += cm;
         }
+        // four entries at a time: their column ids and weights are read
+        // before any is written back (one LDS round trip per four entries),
+        // the diagonal's weight is skipped without a branch
         R sum = 0;
         int32_t dslot = 0;
-        for (int32_t u = 0; u < len; ++u) {
-            if (L.lcol[base + u] == i) {
-                dslot = u;
-                continue;
+        for (int32_t u0 = 0; u0 < len; u0 += 4) {
+            int32_t cu[4];
+            R wu[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const bool in = u0 + k < len;
+                cu[k] = in ? L.lcol[base + u0 + k] : i;
+                wu[k] = in ? L.acc[base + u0 + k] : R(0);
             }
-            const R w = clamp_w(L.acc[base + u], use_clamp, cmin);
-            sum += w;
-            L.acc[base + u] = -w;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const R w = clamp_w(wu[k], use_clamp, cmin);
+                const bool dg = cu[k] == i;
+                if (dg && u0 + k < len) dslot = u0 + k;
+                sum = dg ? sum : sum + w;
+                wu[k] = -w;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (u0 + k < len && cu[k] != i) L.acc[base + u0 + k] = wu[k];
         }
         L.acc[base + dslot] = sum;
         Mdiag[i] = m;
