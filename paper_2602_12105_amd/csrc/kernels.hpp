@@ -80,29 +80,29 @@ __device__ __forceinline__ R clamp_w(R w, int use_clamp, R cmin) {
 }
 
 
-// P1 stiffness of one tetrahedron in its own vertex order: the rows of E^{-1},
-// E = [x1 - x0, x2 - x0, x3 - x0] (as columns), are the gradients of the
-// barycentric functions 1..3: grad phi_1 = (e2 x e3)/det, grad phi_2 =
-// (e3 x e1)/det, grad phi_3 = (e1 x e2)/det, grad phi_0 = -(sum).
+// P1 stiffness of one tetrahedron in its own vertex order. With E =
+// [x1 - x0, x2 - x0, x3 - x0] (as columns) and det = det E, the rows of
+// E^{-1} are the gradients of the barycentric functions 1..3: grad phi_1 =
+// (e2 x e3) / det, grad phi_2 = (e3 x e1) / det, grad phi_3 = (e1 x e2) / det,
+// grad phi_0 = -(sum). K_pq = vol grad phi_p . grad phi_q with vol = |det| / 6
+// is therefore (c_p . c_q) / (6 |det|) for the unscaled cross products c_p:
+// one reciprocal scales the six products instead of the twelve gradient
+// components.
 template <typename R>
-struct TetG {
-    V3<R> g0, g1, g2, g3;
-    R vol, det;
+struct TetC {
+    V3<R> c0, c1, c2, c3;  // det x (the barycentric gradients)
+    R det;
 };
 
 template <typename R>
-__device__ __forceinline__ TetG<R> tet_grads(V3<R> x0, V3<R> x1, V3<R> x2, V3<R> x3) {
+__device__ __forceinline__ TetC<R> tet_cross(V3<R> x0, V3<R> x1, V3<R> x2, V3<R> x3) {
     const V3<R> e1 = sub(x1, x0), e2 = sub(x2, x0), e3 = sub(x3, x0);
-    const V3<R> c23 = cross(e2, e3), c31 = cross(e3, e1), c12 = cross(e1, e2);
-    TetG<R> t;
-    t.det = dot(e1, c23);
-    const R inv = R(1) / t.det;
-    t.g1 = {c23.x * inv, c23.y * inv, c23.z * inv};
-    t.g2 = {c31.x * inv, c31.y * inv, c31.z * inv};
-    t.g3 = {c12.x * inv, c12.y * inv, c12.z * inv};
-    t.g0 = {-(t.g1.x + t.g2.x + t.g3.x), -(t.g1.y + t.g2.y + t.g3.y),
-            -(t.g1.z + t.g2.z + t.g3.z)};
-    t.vol = fabs(t.det) / R(6);
+    TetC<R> t;
+    t.c1 = cross(e2, e3);
+    t.c2 = cross(e3, e1);
+    t.c3 = cross(e1, e2);
+    t.c0 = {-(t.c1.x + t.c2.x + t.c3.x), -(t.c1.y + t.c2.y + t.c3.y), -(t.c1.z + t.c2.z + t.c3.z)};
+    t.det = dot(e1, t.c1);
     return t;
 }
 
@@ -327,7 +327,7 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
                 const V3<R> xb = sel2v(kb == 0, v0, sel2v(kb == 1, v1, v2));
                 L.c(2, q) = voronoi_corner(sub(xa, xi), sub(xb, xi), nn, db * h, da * h, db, da);
             } else {
-                L.c(2, q) = nn / R(6);
+                L.c(2, q) = nn * (R(1) / R(6));  // area / 3
             }
             if (n2 == R(0) && ia && ib) ++ndeg;
         } else {
@@ -341,16 +341,18 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             const int32_t id2 = p <= 1 ? w1 : (p == 2 ? i : w2);
             const int32_t id3 = p <= 2 ? w2 : i;
             const V3<R> x0 = ld3(X, id0), x1 = ld3(X, id1), x2 = ld3(X, id2), x3 = ld3(X, id3);
-            const TetG<R> tg = tet_grads(x0, x1, x2, x3);
+            const TetC<R> tc = tet_cross(x0, x1, x2, x3);
+            const R ad = fabs(tc.det);
+            const R sc = R(1) / (R(6) * ad);  // vol / det^2
             // every pair's product in one fixed operand order, then the three
             // pairs (p, other) in element order
-            const R d01 = dot(tg.g0, tg.g1), d02 = dot(tg.g0, tg.g2), d03 = dot(tg.g0, tg.g3);
-            const R d12 = dot(tg.g1, tg.g2), d13 = dot(tg.g1, tg.g3), d23 = dot(tg.g2, tg.g3);
-            L.c(0, q) = -(tg.vol * sel4(p, d01, d01, d02, d03));
-            L.c(1, q) = -(tg.vol * sel4(p, d02, d12, d12, d13));
-            L.c(2, q) = -(tg.vol * sel4(p, d03, d13, d23, d23));
-            L.c(3, q) = tg.vol / R(4);
-            if (tg.det == R(0) && i < w0 && i < w1 && i < w2) ++ndeg;
+            const R d01 = dot(tc.c0, tc.c1), d02 = dot(tc.c0, tc.c2), d03 = dot(tc.c0, tc.c3);
+            const R d12 = dot(tc.c1, tc.c2), d13 = dot(tc.c1, tc.c3), d23 = dot(tc.c2, tc.c3);
+            L.c(0, q) = -(sc * sel4(p, d01, d01, d02, d03));
+            L.c(1, q) = -(sc * sel4(p, d02, d12, d12, d13));
+            L.c(2, q) = -(sc * sel4(p, d03, d13, d23, d23));
+            L.c(3, q) = ad * (R(1) / R(24));  // vol / 4
+            if (tc.det == R(0) && i < w0 && i < w1 && i < w2) ++ndeg;
         }
     }
     if (ndeg) atomicAdd(n_degenerate, ndeg);
