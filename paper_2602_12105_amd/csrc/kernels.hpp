@@ -152,6 +152,26 @@ struct BlockLds {
     __device__ R &c(int f, int32_t q) { return cw[(size_t)q * CW + f]; }
 };
 
+// Copy n 32-bit words src[0, n) (4-byte aligned) into LDS dst[0, n) with the
+// whole workgroup: the 16-byte aligned middle with 16-byte loads, the up to
+// three words before and after it one by one (no load leaves [src, src + n)).
+__device__ __forceinline__ void stage_words(const uint32_t *__restrict__ src, int32_t n,
+                                            uint32_t *dst) {
+    const int32_t t = threadIdx.x, nt = blockDim.x;
+    const int32_t head = min(n, (int32_t)((4u - (uint32_t)(((uintptr_t)src >> 2) & 3u)) & 3u));
+    const int32_t nv = (n - head) >> 2, tail = head + 4 * nv;
+    if (t < head) dst[t] = src[t];
+    if (t < n - tail) dst[tail + t] = src[tail + t];
+    for (int32_t k = t; k < nv; k += nt) {
+        const uint4 w = *reinterpret_cast<const uint4 *>(src + head + 4 * k);
+        uint32_t *d = dst + head + 4 * k;
+        d[0] = w.x;
+        d[1] = w.y;
+        d[2] = w.z;
+        d[3] = w.w;
+    }
+}
+
 // Row of an incidence record within its block: the record carries its
 // vertex modulo 64 (bits 26-31), and blocks hold a power of two of at most
 // 64 rows starting at a multiple of that size.
@@ -257,12 +277,20 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
         L.lrp[j] = rowptr[r0 + j] - s0;
         L.lvt[j] = vtptr[r0 + j] - q0;
     }
-    for (int32_t j = t; j < span; j += blockDim.x) {
-        const int32_t c = col[s0 + j];
-        L.lcol[j] = c;
-        L.acc[j] = R(0);
+    if constexpr (DIM == 2) {
+        // 16-byte loads (L9 triangles 235 -> 229 us cold; the tetrahedral
+        // kernel, VALU-bound, was slower with them: 1181 -> 1281 us at 160^3)
+        stage_words(reinterpret_cast<const uint32_t *>(col + s0), span,
+                    reinterpret_cast<uint32_t *>(L.lcol));
+        stage_words(inc + q0, ninc, L.lrec);
+        for (int32_t j = t; j < span; j += blockDim.x) L.acc[j] = R(0);
+    } else {
+        for (int32_t j = t; j < span; j += blockDim.x) {
+            L.lcol[j] = col[s0 + j];
+            L.acc[j] = R(0);
+        }
+        for (int32_t q = t; q < ninc; q += blockDim.x) L.lrec[q] = inc[q0 + q];
     }
-    for (int32_t q = t; q < ninc; q += blockDim.x) L.lrec[q] = inc[q0 + q];
     __syncthreads();
     int ndeg = 0;
     // phase A: element terms per incidence, from LDS only
