@@ -235,7 +235,8 @@ constexpr int kAssembleThreads = 256;
 
 inline int64_t assembly_lds_bytes(int dim, int s, int64_t rpb, int64_t span, int64_t ninc) {
     const int cw = dim == 2 ? 3 : 4;
-    return span * (s + 4) + ninc * (cw * s + 4) + 2 * (rpb + 1) * 4 + 64;
+    // + the per-row shift of the contribution records (cw / 2 values a row)
+    return span * (s + 4) + ninc * (cw * s + 4) + rpb * (cw / 2) * s + 2 * (rpb + 1) * 4 + 64;
 }
 
 inline unsigned grid_for(int64_t n, int threads) {

@@ -124,7 +124,13 @@ __device__ __forceinline__ V3<R> sel2v(bool c, V3<R> a, V3<R> b) {
 // LDS layout of the assembly kernels for one block of rows [r0, r1):
 //   cw   : R[inc_max][CW]   per-incidence contributions (phase A), an
 //                           incidence's CW terms side by side, so that phase B
-//                           reads them from one address (16-byte aligned: first)
+//                           reads them from one address (16-byte aligned:
+//                           first); the records of the block's row r are
+//                           shifted by r * SK values (SK = CW / 2: half a
+//                           record), so that phase B's threads, one per row,
+//                           whose records lie a row's incidence count apart
+//                           (24 for interior tet rows: 768 bytes, one bank
+//                           set), spread over the banks
 //   acc  : R[span]          the block's CSR values (accumulated, then finished)
 //   lcol : int32[span]      the block's column ids
 //   lrec : uint32[ninc]     the block's incidence records
@@ -143,13 +149,15 @@ struct BlockLds {
     __device__ BlockLds(unsigned char *smem, int32_t span_max_, int32_t inc_max_, int32_t rpb_)
         : inc_max(inc_max_), span_max(span_max_), rpb(rpb_) {
         cw = (R *)smem;
-        acc = cw + (size_t)inc_max * CW;
+        acc = cw + (size_t)inc_max * CW + (size_t)rpb * SK;
         lcol = (int32_t *)(acc + span_max);
         lrec = (uint32_t *)(lcol + span_max);
         lrp = (int32_t *)(lrec + inc_max);
         lvt = lrp + rpb + 1;
     }
-    __device__ R &c(int f, int32_t q) { return cw[(size_t)q * CW + f]; }
+    static constexpr int SK = CW / 2;
+    // the terms of incidence q of the block's row r
+    __device__ R *rec(int32_t q, int32_t r) { return cw + (size_t)q * CW + r * SK; }
 };
 
 // Copy n 32-bit words src[0, n) (4-byte aligned) into LDS dst[0, n) with the
@@ -300,6 +308,7 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
         const int32_t rr = rec_row(rec, rpb);
         const int32_t i = r0 + rr, base = L.lrp[rr];
         const int32_t la = base + (int32_t)(rec & 255u), lb = base + (int32_t)((rec >> 8) & 255u);
+        R *cq = L.rec(q, rr);
         if constexpr (INTR) {
             // triangle (i, a, b) in cyclic order; edge ids by the rule that
             // slot j of a triangle is the edge opposite its vertex j
@@ -315,7 +324,7 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             const int pa = p == 2 ? 0 : p + 1, pb = p == 0 ? 2 : p - 1;
             const R ei = X[fe[p]], ea = X[fe[pa]], eb = X[fe[pb]];  // opposite i, a, b
             R A;
-            intrinsic_terms(ei, ea, eb, mass_kind == 1, L.c(0, q), L.c(1, q), A, L.c(2, q));
+            intrinsic_terms(ei, ea, eb, mass_kind == 1, cq[0], cq[1], A, cq[2]);
             if (A == R(0) && i < L.lcol[la] && i < L.lcol[lb]) ++ndeg;
             continue;
         }
@@ -346,16 +355,16 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             const int kb = (b > a) + (b > i), ka = (a > b) + (a > i);
             const R db = kb == 0 ? d0 : (kb == 1 ? d1 : d2);
             const R da = ka == 0 ? d0 : (ka == 1 ? d1 : d2);
-            L.c(0, q) = db * h;
-            L.c(1, q) = da * h;
+            cq[0] = db * h;
+            cq[1] = da * h;
             if (mass_kind == 1) {
                 const int ki = (i > a) + (i > b);
                 const V3<R> xi = sel2v(ki == 0, v0, sel2v(ki == 1, v1, v2));
                 const V3<R> xa = sel2v(ka == 0, v0, sel2v(ka == 1, v1, v2));
                 const V3<R> xb = sel2v(kb == 0, v0, sel2v(kb == 1, v1, v2));
-                L.c(2, q) = voronoi_corner(sub(xa, xi), sub(xb, xi), nn, db * h, da * h, db, da);
+                cq[2] = voronoi_corner(sub(xa, xi), sub(xb, xi), nn, db * h, da * h, db, da);
             } else {
-                L.c(2, q) = nn * (R(1) / R(6));  // area / 3
+                cq[2] = nn * (R(1) / R(6));  // area / 3
             }
             if (n2 == R(0) && ia && ib) ++ndeg;
         } else {
@@ -376,10 +385,10 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             // pairs (p, other) in element order
             const R d01 = dot(tc.c0, tc.c1), d02 = dot(tc.c0, tc.c2), d03 = dot(tc.c0, tc.c3);
             const R d12 = dot(tc.c1, tc.c2), d13 = dot(tc.c1, tc.c3), d23 = dot(tc.c2, tc.c3);
-            L.c(0, q) = -(sc * sel4(p, d01, d01, d02, d03));
-            L.c(1, q) = -(sc * sel4(p, d02, d12, d12, d13));
-            L.c(2, q) = -(sc * sel4(p, d03, d13, d23, d23));
-            L.c(3, q) = ad * (R(1) / R(24));  // vol / 4
+            cq[0] = -(sc * sel4(p, d01, d01, d02, d03));
+            cq[1] = -(sc * sel4(p, d02, d12, d12, d13));
+            cq[2] = -(sc * sel4(p, d03, d13, d23, d23));
+            cq[3] = ad * (R(1) / R(24));  // vol / 4
             if (tc.det == R(0) && i < w0 && i < w1 && i < w2) ++ndeg;
         }
     }
@@ -399,7 +408,7 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             // before their adds (which read nothing back), in incidence order
             for (; q + 1 < qe; q += 2) {
                 const uint32_t ra = L.lrec[q], rb = L.lrec[q + 1];
-                const R *ca = L.cw + (size_t)q * CW, *cb = ca + CW;
+                const R *ca = L.rec(q, rr), *cb = ca + CW;
                 const R a0 = ca[0], a1 = ca[1], a2 = ca[2], am = ca[CW - 1];
                 const R b0 = cb[0], b1 = cb[1], b2 = cb[2], bm = cb[CW - 1];
                 atomicAdd(&L.acc[base + (ra & 255u)], a0);
@@ -416,7 +425,7 @@ __device__ void assemble_block(const AsmView &v, uint32_t tile, const R *__restr
             const uint32_t rec = L.lrec[q];
             // the incidence's terms are read before any add into the row's
             // slots, so that the reads go out together
-            const R *cq = L.cw + (size_t)q * CW;
+            const R *cq = L.rec(q, rr);
             const R c0 = cq[0], c1 = cq[1], c2 = cq[2], cm = cq[CW - 1];
             if constexpr (sizeof(R) == 8) {
                 // FP64: LDS adds without return (one LDS round trip per
