@@ -24,8 +24,19 @@ namespace {
 
 using namespace kern;
 
+// Threads per workgroup of the assembly kernels (rows per block and block
+// LDS are fixed by the mesh): measured at the icosphere L9, the 256 x L5
+// batch and the Kuhn cube 160^3 against 128 / 192 / 256 / 384 / 512 threads.
+// FP64: 192 (L9 triangles 226 -> 216 us cold, tets 1149 -> 1106 us against
+// 256); FP32 triangles: 128 (184 -> 150 us); FP32 tets (blocks of 32 rows):
+// 256 (192: 788 -> 880 us).
 template <typename R, int DIM>
-__global__ void __launch_bounds__(kAssembleThreads)
+constexpr int asm_threads() {
+    return sizeof(R) == 8 ? 192 : (DIM == 2 ? 128 : 256);
+}
+
+template <typename R, int DIM>
+__global__ void __launch_bounds__((asm_threads<R, DIM>()))
 k_assemble(AsmView v, int32_t nblocks, int64_t nnz, const R *__restrict__ X,
            R *__restrict__ Kvals, R *__restrict__ Mdiag, int use_clamp, R cmin,
            int32_t *__restrict__ n_degenerate, int mass_kind) {
@@ -39,7 +50,7 @@ k_assemble(AsmView v, int32_t nblocks, int64_t nnz, const R *__restrict__ X,
 
 // Intrinsic variant: the same row blocks with edge lengths as input.
 template <typename R>
-__global__ void __launch_bounds__(kAssembleThreads)
+__global__ void __launch_bounds__((asm_threads<R, 2>()))
 k_assemble_intrinsic(AsmView v, int32_t nblocks, int64_t nnz, int64_t nE,
                      const int32_t *__restrict__ inc_elem, const int32_t *__restrict__ elem_edge,
                      const R *__restrict__ lengths, R *__restrict__ Kvals, R *__restrict__ Mdiag,
@@ -310,12 +321,12 @@ dgo_status launch_assemble(const dgo_mesh *m, int32_t batch, const void *X,
     if (m->dim == 2)
     {
         auto kfn = k_assemble<R, 2>;
-        DGO_LAUNCH_EXT("assemble_tri", s, kfn, grid, dim3(kAssembleThreads), (uint32_t)lds, v,
+        DGO_LAUNCH_EXT("assemble_tri", s, kfn, grid, dim3(asm_threads<R, 2>()), (uint32_t)lds, v,
                        nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg, mk);
     }
     else
         DGO_LAUNCH("assemble_tet", s,
-                   k_assemble<R, 3><<<grid, kAssembleThreads, lds, s>>>(
+                   k_assemble<R, 3><<<grid, asm_threads<R, 3>(), lds, s>>>(
                        v, nblocks, m->nnz, (const R *)X, (R *)K, (R *)M, uc, cm, ndeg, 0));
     DGO_HIP(hipGetLastError());
     return DGO_OK;
@@ -332,7 +343,7 @@ dgo_status launch_assemble_intrinsic(const dgo_mesh *m, int32_t batch, const voi
     const R cm = o ? (R)o->clamp_min : R(0);
     const int mk = o ? o->mass : 0;
     DGO_LAUNCH("assemble_intrinsic", s,
-               k_assemble_intrinsic<R><<<grid, kAssembleThreads, lds, s>>>(
+               k_assemble_intrinsic<R><<<grid, asm_threads<R, 2>(), lds, s>>>(
                    view_of(m), m->nblocks, m->nnz, m->nE, m->inc_elem, m->elem_edge,
                    (const R *)lengths, (R *)K, (R *)M, uc, cm, ndeg, mk));
     DGO_HIP(hipGetLastError());
