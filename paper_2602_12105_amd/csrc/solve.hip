@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(TR)
 k_spmm8_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
              const int32_t *__restrict__ col, int32_t nV, int64_t nnz, R alpha,
              const R *__restrict__ M, R beta, const R *__restrict__ K, const R *__restrict__ x,
-             R *__restrict__ y) {
+             R *__restrict__ y, int il) {
     constexpr int G = 8, GPB = TR / G;
     constexpr int V = Piece<R>::V, LPR = 8 / V;
     const int64_t bt = blockIdx.y;
@@ -150,8 +150,8 @@ k_spmm8_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     y += bt * (int64_t)nV * 8;
     const int lane = threadIdx.x % G, grp = threadIdx.x / G;
     const int gbase = (threadIdx.x & 63) - lane;
-    int64_t t0, t1;
-    tile_range(((int64_t)nV + GPB - 1) / GPB, t0, t1);
+    const TileSeq ts = tile_seq(((int64_t)nV + GPB - 1) / GPB, il);
+    const int64_t t0 = ts.t0, t1 = ts.t1, st_ = ts.step;
     // the lane group's row of a tile (len 0: none; a row holds at least its diagonal)
     auto desc = [&](int64_t tile, int2 &d, int32_t &len) {
         const int64_t r = tile * GPB + grp;
@@ -178,16 +178,16 @@ k_spmm8_pipe(const int2 *__restrict__ rdesc, const uint8_t *__restrict__ rlen,
     int2 dA, dB;
     int32_t lA, lB;
     desc(t0, dA, lA);
-    desc(t0 + 1, dB, lB);
+    desc(t0 + st_, dB, lB);
     int32_t cjA;
     R kA, mA;
     first(dA, lA, cjA, kA, mA);
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    for (int64_t tile = t0; tile < t1; tile += st_) {
         if (lA == 0) break;  // past nV: uniform over the lane group, and so are later tiles
         int2 dC;
         int32_t lC, cjB;
         R kB, mB;
-        desc(tile + 2, dC, lC);
+        desc(tile + 2 * st_, dC, lC);
         first(dB, lB, cjB, kB, mB);
         const int32_t i = dA.x;
         const R dt = alpha * mA;
@@ -850,15 +850,22 @@ int64_t ntiles(int64_t nV, int rows_per_tile) { return (nV + rows_per_tile - 1) 
 // XCD's workgroups once the gathered vector of one XCD's share of the rows is
 // larger than half its 4 MB L2, else a contiguous chunk per workgroup. These
 // grids hold one or two workgroups per CU with many tiles each (w = A z at
-// the icosphere L9, 8 FP64 columns: 186 -> 172 us per iteration). The SpMM
-// grids are not persistent (workgroups of about five tiles, dispatched in
-// order), so their resident workgroups already work on neighbouring chunks;
-// interleaving them was slower (L9, 8 columns: 201 -> 210 us).
+// the icosphere L9, 8 FP64 columns: 186 -> 172 us per iteration). The other
+// SpMM grids are not persistent (workgroups of about five tiles, dispatched
+// in order), so their resident workgroups already work on neighbouring
+// chunks; interleaving them was slower (L9, 8 columns: 201 -> 210 us); the
+// 8-column pipeline instead turns persistent with interleaved tiles past the
+// L2 (kSpmmPersistBlocks).
 constexpr int64_t kXcdL2Bytes = 4 << 20;
 
 int gather_il(const dgo_mesh *m, int k, size_t es) {
     return (int64_t)m->nV * k * (int64_t)es / 8 > kXcdL2Bytes / 2 ? 1 : 0;
 }
+
+// Workgroups of the 8-column SpMM when its tiles are interleaved: one per CU
+// (icosphere L9: 201 -> 193 us warm, 241 -> 235 us cold against the grid of
+// about five tiles per workgroup; 512 workgroups: 231 / 287 us, 1024: 236 / 299)
+constexpr int kSpmmPersistBlocks = 256;
 
 // ------------------------------------------------------------- dispatch
 
@@ -876,10 +883,12 @@ void launch_spmm_kp(const dgo_mesh *m, int32_t batch, R alpha, const R *M, R bet
         // CU (L7: 256 workgroups, 10.2 vs 14.1 us for the k_spmm grid; L9:
         // 4096, 201 vs 206 us; 256 at L9, 80 tiles each: 267 us)
         const int64_t nt8 = ntiles(m->nV, TR / 8);
-        dim3 grid8(nblocks_for(nt8, std::max<int64_t>(256, nt8 / 5)), (unsigned)batch);
+        const int il8 = gather_il(m, k, sizeof(R));
+        dim3 grid8(nblocks_for(nt8, il8 ? (int64_t)kSpmmPersistBlocks : std::max<int64_t>(256, nt8 / 5)),
+                   (unsigned)batch);
         auto kfn8 = k_spmm8_pipe<R>;
         DGO_LAUNCH_EXT("spmm", s, kfn8, grid8, dim3(TR), 0u, m->rdesc, m->rlen, m->col, m->nV, m->nnz,
-                       alpha, M, beta, K, x, y);
+                       alpha, M, beta, K, x, y, il8);
         return;
     }
     if (KP == 1 && short_rows) {  // one column: the same pipeline, a lane per entry
