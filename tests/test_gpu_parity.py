@@ -284,6 +284,30 @@ def test_pcg_fixed_iterations_match_oracle(dtype, iters):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pcg_interleaved_tiles_match_oracle(dtype):
+    """Icosphere L8 with 8 columns: an XCD's share of the gathered vector
+    (655,362 rows x 8 values / 8 XCDs) exceeds 2 MB, so the PCG kernels that
+    gather walk tiles interleaved over each XCD's workgroups. Fixed iteration
+    count, element by element against the oracle."""
+    print(f"[pcg-interleaved] ico8 {dtype}", flush=True)
+    m, K, M, b = _cfg2_system(8, 8, dtype, seed=6)
+    assert m.nV * 8 * (8 if dtype == "f64" else 4) // 8 > 2 * 1024 * 1024
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=0.0, max_iter=20, fixed_iters=True)
+    assert rep["iters"] == [20] * 8
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    uo, _, _ = oracle.pcg(rp, col, 1.0, M.double().cpu().numpy(), 1e-3, K.double().cpu().numpy(),
+                          b.double().cpu().numpy(), rtol=0.0, max_iter=20)
+    w = assert_cols_close(u.double().cpu().numpy(), uo, RTOL[dtype])
+    print(f"  worst column-scaled error {w:.2e}", flush=True)
+    # the 8-column SpMM past the L2 (persistent, interleaved tiles)
+    y = dgo.spmv(m, 0.7, M, 1.3, K, b).double().cpu().numpy()
+    Kh, Mh, bh = K.double().cpu().numpy(), M.double().cpu().numpy(), b.double().cpu().numpy()
+    yo = oracle.spmv(rp, col, 0.7, Mh, 1.3, Kh, bh).reshape(y.shape)
+    sc = spmv_scale(rp, col, 0.7, Mh, 1.3, Kh, bh).reshape(y.shape)
+    assert np.all(np.abs(y - yo) <= RTOL[dtype] * sc)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("k", [13, 16])
 def test_pcg_k13_match_oracle(dtype, k):
     """13 or 16 columns (lane groups of 16 over padded rows of 7 entries: the
