@@ -111,4 +111,9 @@ MESHES = {
     "fan40": lambda: _fan(40, 2),
     "grid130fan": lambda: _grid_with_fan(130, 30, 3),
     "ico6fan": lambda: _icosphere_with_fan(6, 30, 3),
+    # the largest supported vertex degree, 254 (row-local ranks of 8 bits):
+    # a closed fan, and a vertex joined to 254 vertices of a mesh swept in
+    # breadth-first row order
+    "fan254": lambda: _fan(254, 4),
+    "ico6fan254": lambda: _icosphere_with_fan(6, 253, 6),
 }

@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2602_12105_amd as dgo  # noqa: E402  (no skip: a broken import fails the suite)
 DEV = "cuda:0"
-TRI = ["tri1", "fan", "fan40", "grid7", "grid64", "grid130fan", "ico3", "ico7"]
+TRI = ["tri1", "fan", "fan40", "grid7", "grid64", "grid130fan", "ico3", "ico7", "fan254"]
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -65,7 +65,13 @@ def test_mesh_errors():
     with pytest.raises(dgo.DgoError) as e:
         dgo.Mesh(F, 5)
     assert e.value.status == "INVALID_ARG"
-    # degree above 254 is reported as unsupported
+    # degree above 254 is reported as unsupported: a closed fan whose centre
+    # has degree 255 (degree 254 is covered by the parity tests), and an open
+    # fan of 299
+    F = torch.tensor([[0, 1 + i, 1 + (i + 1) % 255] for i in range(255)], dtype=torch.int32, device=DEV)
+    with pytest.raises(dgo.DgoError) as e:
+        dgo.Mesh(F, 256)
+    assert e.value.status == "UNSUPPORTED"
     n = 300
     F = torch.tensor([[0, i, i + 1] for i in range(1, n)], dtype=torch.int32, device=DEV)
     with pytest.raises(dgo.DgoError) as e:
@@ -108,7 +114,7 @@ def _assemble_check(name, dtype, batch=1, clamp=None):
 
 
 @pytest.mark.parametrize("name", ["tri1", "tet1", "disjoint", "fan", "grid7", "grid64", "ico3",
-                                  "ico7", "cube3", "cube9", "cube64"])
+                                  "ico7", "cube3", "cube9", "cube64", "fan254", "ico6fan254"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_assemble_parity(name, dtype):
     print(f"[assemble] {name} {dtype}", flush=True)
@@ -170,7 +176,7 @@ def test_spmv_parity_breadth_first_rows(k, dtype):
     test_spmv_parity("ico7", k, dtype)
 
 
-@pytest.mark.parametrize("name", ["fan40", "grid130fan", "ico6fan"])
+@pytest.mark.parametrize("name", ["fan40", "grid130fan", "ico6fan", "fan254", "ico6fan254"])
 @pytest.mark.parametrize("k", [1, 8])
 def test_spmv_parity_long_rows(name, k):
     """Rows of more than 16 entries (a fan centre)."""
@@ -324,7 +330,7 @@ def test_pcg_k13_match_oracle(dtype, k):
     assert max(rep["true_relres"]) < 1.0
 
 
-@pytest.mark.parametrize("name", ["fan40", "grid130fan", "ico6fan"])
+@pytest.mark.parametrize("name", ["fan40", "grid130fan", "ico6fan", "fan254"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_pcg_long_rows_match_oracle(name, dtype):
     """Meshes with a row of more than 16 entries iterate over CSR rows (in
@@ -602,12 +608,18 @@ def _fans(n_fans, spokes, seed):
     return X, np.array(F, np.int32)
 
 
-@pytest.mark.parametrize("shape", ["ico4", "fans"])
+@pytest.mark.parametrize("shape", ["ico4", "fans", "fan254"])
 def test_vjp_row_block_and_long_rows(shape):
     """The row-block VJP (ico4) and the per-row form it falls back to when a
-    row block of very long rows does not fit its LDS budget (fans)."""
+    row block of very long rows does not fit its LDS budget (fans); fan254
+    has a vertex of the largest supported degree."""
     print(f"[vjp] {shape}", flush=True)
-    X, F = meshgen.icosphere(4, 1e-2, 5) if shape == "ico4" else _fans(64, 150, 5)
+    if shape == "ico4":
+        X, F = meshgen.icosphere(4, 1e-2, 5)
+    elif shape == "fans":
+        X, F = _fans(64, 150, 5)
+    else:
+        X, F = MESHES[shape]()
     m = dgo.Mesh(torch.from_numpy(F).to(DEV), X.shape[0])
     Xd = torch.from_numpy(X).to(DEV)
     gK = torch.from_numpy(meshgen.normal(13, m.nnz)).to(DEV)
