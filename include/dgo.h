@@ -215,7 +215,7 @@ dgo_status dgo_assemble_vjp(const dgo_mesh *mesh, dgo_dtype dtype, int32_t batch
  * j is 1/2 cot = (l_{j+1}^2 + l_{j+2}^2 - l_j^2) / (8 A); K and M then follow
  * as in dgo_assemble (w_ij summed over the triangles on edge ij, M_ii = sum of
  * A / 3). d_lengths (batch x nE) is indexed like the mesh's edges
- * (dgo_mesh_edges order); d_Kvals (batch x nnz), d_Mdiag (batch x nV). opts
+ * (dgo_mesh_edges order; may be NULL when the mesh has no edges); d_Kvals (batch x nnz), d_Mdiag (batch x nV). opts
  * and h_n_degenerate as in dgo_assemble (lengths that violate the triangle
  * inequality count as zero-area triangles). Bitwise deterministic and
  * symmetric. The first call on a mesh allocates its per-incidence face list
@@ -252,7 +252,8 @@ dgo_status dgo_conformal_laplacian(const dgo_mesh *mesh, dgo_dtype dtype, const 
  * x_{j+1} the edge opposite local vertex j. d_X (nV x 3), d_u (nV x k,
  * row-major), 1 <= k <= 64; d_g (k x 3 x nF, component-major: component d of
  * field c on face f at [(c * 3 + d) * nF + f], the (3, nF) face-field layout
- * of that example) is overwritten. Triangle meshes only (else
+ * of that example) is overwritten; it may be NULL when the mesh has no
+ * faces (then nothing is done). Triangle meshes only (else
  * DGO_ERR_UNSUPPORTED). Zero-area faces give non-finite values. */
 dgo_status dgo_face_gradient(const dgo_mesh *mesh, dgo_dtype dtype, const void *d_X, int32_t k,
                              const void *d_u, void *d_g, dgo_stream stream);
@@ -260,7 +261,8 @@ dgo_status dgo_face_gradient(const dgo_mesh *mesh, dgo_dtype dtype, const void *
 /* Divergence D = G^T diag(A_f) (the divergence operator of Sec. 7.4, with the
  * sign its u-update needs when the Laplacian is the SPD stiffness: D G = K):
  * (D y)_i = sum over the faces f of vertex i of A_f grad phi_i . y_f. d_y
- * (k x 3 x nF, the layout of dgo_face_gradient's output), d_div (nV x k) is
+ * (k x 3 x nF, the layout of dgo_face_gradient's output; may be NULL when
+ * the mesh has no faces: then every sum is 0), d_div (nV x k) is
  * overwritten. Each sum runs over the vertex's faces in ascending face order:
  * deterministic. The per-face corner terms are staged in the mesh's
  * workspace (3 k nF values, grown on demand and shared with the mesh's other

@@ -391,7 +391,7 @@ extern "C" dgo_status dgo_assemble_intrinsic(const dgo_mesh *m, dgo_dtype dtype,
                                              void *d_Kvals, void *d_Mdiag, int64_t *h_n_degenerate,
                                              dgo_stream stream) {
     clear_error();
-    if (!m || !d_lengths || !d_Kvals || !d_Mdiag)
+    if (!m || (!d_lengths && m->nE > 0) || !d_Kvals || !d_Mdiag)
         return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_intrinsic: NULL argument");
     if (dtype != DGO_F32 && dtype != DGO_F64)
         return fail(DGO_ERR_INVALID_ARG, "dgo_assemble_intrinsic: bad dtype");

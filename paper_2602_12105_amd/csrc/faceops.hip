@@ -114,9 +114,11 @@ k_vertex_gather(const int32_t *__restrict__ vtptr, int32_t nV, int64_t n_inc, in
     div[o] = acc;
 }
 
-dgo_status check_args(const dgo_mesh *m, dgo_dtype dtype, const void *a, int32_t k, const void *b,
-                      const void *c, const std::string &who) {
-    if (!m || !a || !b || !c) return fail(DGO_ERR_INVALID_ARG, who + ": NULL argument");
+// X, the vertex fields and the face fields; the face fields' pointer may be
+// NULL when the mesh has no faces
+dgo_status check_args(const dgo_mesh *m, dgo_dtype dtype, const void *X, int32_t k, const void *vf,
+                      const void *ff, const std::string &who) {
+    if (!m || !X || !vf || (!ff && m->n_elem > 0)) return fail(DGO_ERR_INVALID_ARG, who + ": NULL argument");
     if (dtype != DGO_F32 && dtype != DGO_F64) return fail(DGO_ERR_INVALID_ARG, who + ": bad dtype");
     if (k < 1 || k > 64) return fail(DGO_ERR_INVALID_ARG, who + ": k must be in [1, 64]");
     if (m->dim != 2) return fail(DGO_ERR_UNSUPPORTED, who + ": triangle meshes only");
@@ -150,7 +152,7 @@ extern "C" dgo_status dgo_face_divergence(const dgo_mesh *m, dgo_dtype dtype, co
                                           int32_t k, const void *d_y, void *d_div,
                                           dgo_stream stream) {
     clear_error();
-    DGO_TRY(check_args(m, dtype, d_X, k, d_y, d_div, "dgo_face_divergence"));
+    DGO_TRY(check_args(m, dtype, d_X, k, d_div, d_y, "dgo_face_divergence"));
     hipStream_t s = (hipStream_t)stream;
     dgo_mesh *mm = const_cast<dgo_mesh *>(m);
     const int64_t nF = m->n_elem, n = (int64_t)m->nV * k;

@@ -142,6 +142,37 @@ def test_assemble_symmetry_full_and_determinism():
     np.testing.assert_array_equal(K[order], K)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_empty_element_set(dim):
+    """Vertices and no elements: no edges, a diagonal-only pattern, K = 0 and
+    M = 0, a zero operator; for triangles also the intrinsic assembly from
+    no lengths, the VJP, and G and D on empty face fields (D = 0)."""
+    print(f"[empty] dim={dim}", flush=True)
+    nV = 5
+    m = dgo.Mesh(torch.empty((0, dim + 1), dtype=torch.int32, device=DEV), nV)
+    assert (m.n_elem, m.nE, m.nnz, m.max_row) == (0, 0, nV, 1)
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    np.testing.assert_array_equal(rp, np.arange(nV + 1))
+    np.testing.assert_array_equal(col, np.arange(nV))
+    EV, ee, _ = m.edges()
+    assert EV.shape == (0, 2) and ee.shape == (0, m.nl)
+    X = torch.from_numpy(meshgen.normal(3, nV * 3).reshape(nV, 3)).to(DEV)
+    for td in (torch.float64, torch.float32):
+        Xt = X.to(td)
+        K, M = dgo.assemble(m, Xt)
+        assert K.shape == (nV,) and M.shape == (nV,) and not K.any() and not M.any()
+        x = torch.ones(nV, 2, dtype=td, device=DEV)
+        assert not dgo.spmv(m, 0.7, M, 1.3, K, x).any()
+        if dim == 2:
+            Ki, Mi = dgo.assemble_intrinsic(m, torch.empty(0, dtype=td, device=DEV))
+            assert not Ki.any() and not Mi.any()
+            assert not dgo.assemble_vjp(m, Xt, torch.ones_like(K), torch.ones_like(M)).any()
+            g = dgo.face_gradient(m, Xt, x)
+            assert g.shape == (2, 3, 0)
+            d = dgo.face_divergence(m, Xt, g)
+            assert d.shape == (nV, 2) and not d.any()
+
+
 def test_degenerate_reported():
     X = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0, 1, 0]], float)
     F = torch.tensor([[0, 1, 2], [0, 1, 3]], dtype=torch.int32, device=DEV)
