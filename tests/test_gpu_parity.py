@@ -534,6 +534,33 @@ def test_pcg_dirichlet_cube_f32_attainable(n):
     assert np.array_equal(u.double().cpu().numpy()[bm], gh[bm])
 
 
+def test_pcg_zero_column_and_zero_iterations():
+    """Degenerate solves. A zero right-hand side with a zero initial guess
+    meets ||r|| <= max(rtol ||b||, atol) = 0 before any iteration: 0
+    iterations, converged, u = 0 exactly, residual 0; the other columns of the
+    block iterate as usual (the oracle's iterate of the same count, counts
+    within one of the oracle's own stop). max_iter = 0 returns the initial
+    guess unchanged and reports no convergence."""
+    print("[pcg] zero column, zero iterations", flush=True)
+    m, K, M, b = _cfg2_system(4, 8, "f64")
+    b[:, 2] = 0
+    rp, col = [t.cpu().numpy() for t in m.csr()]
+    Kh, Mh, bh = K.cpu().numpy(), M.cpu().numpy(), b.cpu().numpy()
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, rtol=1e-8, max_iter=2000)
+    assert rep["converged_all"], rep
+    assert int(rep["iters"][2]) == 0 and rep["relres"][2] == 0.0 and rep["true_relres"][2] == 0.0
+    assert not u[:, 2].any()
+    uo = _oracle_same_iters(rp, col, 1.0, Mh, 1e-3, Kh, bh, rep["iters"])
+    assert_cols_close(u.cpu().numpy(), uo, RTOL["f64"])
+    for c in (0, 5):
+        _, its, _ = oracle.pcg(rp, col, 1.0, Mh, 1e-3, Kh, bh[:, c].copy(), rtol=1e-8, max_iter=2000)
+        assert abs(int(rep["iters"][c]) - int(its[0])) <= 1
+    u0 = torch.from_numpy(meshgen.normal(8, bh.size).reshape(bh.shape)).to(DEV)
+    u, rep = dgo.pcg(m, 1.0, M, 1e-3, K, b, u0=u0, rtol=1e-8, max_iter=0)
+    assert torch.equal(u, u0)
+    assert not rep["converged_all"] and all(int(i) == 0 for i in rep["iters"])
+
+
 def test_pcg_strict_and_deterministic():
     m, K, M, b = _cfg2_system(4, 3, "f64")
     with pytest.raises(dgo.DgoError) as e:
