@@ -368,6 +368,7 @@ struct Tmp {
     Tmp(const Alloc &a, hipStream_t st) : al(a), s(st) {}
     template <typename X>
     X *get(int64_t count) {
+        if (n == 16) return nullptr;  // the caller reports it as an allocation failure
         void *q = al.get((size_t)(count > 0 ? count : 1) * sizeof(X), s);
         if (q) p[n++] = q;
         return (X *)q;
