@@ -529,7 +529,31 @@ def suite(args, dgo, torch, meshgen):
     ev1.record()
     torch.cuda.synchronize()
     ua = ev0.elapsed_time(ev1) * 1e3 / 20
+    # the same 100 SpMVs captured once as a graph and replayed (five replays,
+    # the median per SpMV), every replay checked bitwise against the eager y
+    y_ref = y.clone()
+    graph = {"spmv_us_per_call": None}
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(100):
+                dgo.spmv(m, 0.0, M, 1.0, K, x, out=y)
+        times, same = [], True
+        for _ in range(5):
+            y.zero_()
+            torch.cuda.synchronize()
+            ev0.record()
+            g.replay()
+            ev1.record()
+            torch.cuda.synchronize()
+            times.append(ev0.elapsed_time(ev1) * 1e3 / 100)
+            same = same and torch.equal(y, y_ref)
+        graph = {"spmv_us_per_call": sorted(times)[2], "replays": 5, "replays_equal_eager": same}
+        del g
+    except Exception as e:  # a launch the capture refuses: reported, not fatal
+        graph["error"] = str(e)[:200]
     out["grid64"] = {"spmv_us_gpu_per_call": us, "spmv_us_wall_per_call": wall, "assemble_us": ua,
+                     "spmv_graph_x100": graph,
                      "note": "latency-bound size (0.4 MB per SpMV): reported in microseconds"}
     del m
 
