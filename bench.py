@@ -277,6 +277,7 @@ def main():
         "pcg_steps": past,
         "kernel_sweeps": sweeps,
         "stream_copy_gbps": copy_gbs,
+        "device": device_info(torch, dev),
         "baseline_note": PAPER_NOTE,
     }
 
@@ -294,6 +295,18 @@ def main():
             torch.add(a, 1.0, out=b_)
         torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
+
+
+def device_info(torch, dev):
+    """The GPU the numbers were taken on, as the runtime reports it (the peak
+    figures used above are the chip's published ones)."""
+    p = torch.cuda.get_device_properties(dev)
+    info = {"name": p.name, "compute_units": p.multi_processor_count,
+            "memory_gib": round(p.total_memory / 2 ** 30, 1)}
+    arch = getattr(p, "gcnArchName", None)
+    if arch:
+        info["arch"] = arch
+    return info
 
 
 def pcg_step(args, dgo, torch, meshgen, level, dtype, steps, warmup):
