@@ -410,18 +410,28 @@ def pcg_step(args, dgo, torch, meshgen, level, dtype, steps, warmup):
 
 
 def kernel_time(dgo, torch, fn, name, reps, flush=None):
-    """Average duration (us) of the library kernel `name` over reps calls of fn,
-    from the library's hipEvents; with flush, 1 GiB is written before each."""
+    """Median over reps calls of fn of the duration (us) of the library kernel
+    `name`, each call's from the library's hipEvents around its launches (read
+    after every call); with flush, 1 GiB is written before each call."""
     dgo.trace_reset()
     dgo.trace_enable(True, name)
+    ds = []
     for _ in range(reps):
         if flush is not None:
             flush.zero_()
+        dgo.trace_reset()  # the totals below are this call's alone
         fn()
+        e = dgo.trace_read().get(name)  # synchronises this call's events
+        if e is not None and e["count"] > 0:
+            ds.append(e["total_ms"] / e["count"] * 1e3)
     torch.cuda.synchronize()
     dgo.trace_enable(False)
-    e = dgo.trace_read().get(name)
-    return None if e is None else e["total_ms"] / e["count"] * 1e3
+    dgo.trace_reset()
+    if not ds:
+        return None
+    ds.sort()
+    n = len(ds)
+    return ds[n // 2] if n % 2 else 0.5 * (ds[n // 2 - 1] + ds[n // 2])
 
 
 def roof(ab, us):
